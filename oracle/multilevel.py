@@ -1,0 +1,141 @@
+"""Galerkin hierarchy, V(k,k)-cycle and preconditioned CG (paper Sec. 5,
+opening paragraphs: Galerkin coarse operators A_{l-1} = R_l A_l P_l with
+R_l = P_l^T; V(k,k) cycles with fourth-kind Chebyshev smoothing; CG as the
+outer solver for symmetric cycles, Sec. 6).
+
+Readings: the coarsest level is solved exactly by a dense Cholesky
+factorisation; every level carries its own block-FSAI factor G_l and its own
+bound beta_l; the coarse initial guess is zero; PCG stops on the recursive
+residual ||r||_2 <= rtol ||b||_2 with x0 = 0.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+from . import chebyshev
+from .bsr import Bsr, from_scipy
+
+
+def galerkin(a: Bsr, p_s: sp.csr_matrix) -> Bsr:
+    """A_c = P^T A P with P = P_s (x) I_b."""
+    pb = sp.csr_matrix(sp.kron(p_s, sp.identity(a.b), format="csr"))
+    ac = pb.T @ a.scipy().tocsr() @ pb
+    ac = sp.csr_matrix(ac)
+    ac.sort_indices()
+    return from_scipy(ac, a.b)
+
+
+@dataclass
+class Level:
+    a: Bsr
+    g: Bsr | None = None          # block-FSAI factor (None on the coarsest level)
+    beta: float = 0.0
+    p_s: sp.csr_matrix | None = None   # prolongation from level l+1 to level l
+    chol: tuple | None = None
+    a_sp: sp.bsr_matrix = field(default=None, repr=False)
+    g_sp: sp.bsr_matrix = field(default=None, repr=False)
+    gt_sp: sp.bsr_matrix = field(default=None, repr=False)
+    pb: sp.csr_matrix = field(default=None, repr=False)
+
+    def finish(self):
+        self.a_sp = self.a.scipy()
+        if self.g is not None:
+            self.g_sp = self.g.scipy()
+            self.gt_sp = self.g_sp.T.tobsr(blocksize=(self.a.b, self.a.b))
+        if self.p_s is not None:
+            self.pb = sp.csr_matrix(sp.kron(self.p_s, sp.identity(self.a.b), format="csr"))
+        return self
+
+    def apply_a(self, v):
+        return self.a_sp @ v
+
+    def apply_m(self, v):
+        return self.gt_sp @ (self.g_sp @ v)
+
+
+def coarse_factor(a: Bsr):
+    return sla.cho_factor(a.dense(), lower=True)
+
+
+def vcycle(levels: list[Level], l: int, b, k: int):
+    """V(k,k) with zero initial guess: pre-smooth, residual, restrict,
+    recurse, prolongate, post-smooth; exact solve on the coarsest level."""
+    lev = levels[l]
+    if l == len(levels) - 1:
+        return sla.cho_solve(lev.chol, b)
+    x = chebyshev.cheb4(lev.apply_a, lev.apply_m, b, None, lev.beta, k, x_is_zero=True)
+    r = b - lev.apply_a(x)
+    xc = vcycle(levels, l + 1, lev.pb.T @ r, k)
+    x = x + lev.pb @ xc
+    x = chebyshev.cheb4(lev.apply_a, lev.apply_m, b, x, lev.beta, k)
+    return x
+
+
+def vcycle_x(levels: list[Level], b, x, k: int):
+    """One V(k,k) cycle from a given initial guess x on level 0."""
+    lev = levels[0]
+    if len(levels) == 1:
+        return sla.cho_solve(lev.chol, b)
+    x = chebyshev.cheb4(lev.apply_a, lev.apply_m, b, x, lev.beta, k)
+    r = b - lev.apply_a(x)
+    xc = vcycle(levels, 1, lev.pb.T @ r, k)
+    x = x + lev.pb @ xc
+    return chebyshev.cheb4(lev.apply_a, lev.apply_m, b, x, lev.beta, k)
+
+
+def pcg(apply_a, apply_prec, b, rtol: float, maxit: int, flexible: bool = False):
+    """Preconditioned CG from x0 = 0. Fletcher-Reeves beta, or Polak-Ribiere
+    (z, r - r_old)/(r_old, z_old) when flexible. Returns
+    (x, iterations, recursive residual history, true relative residual)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = float(np.linalg.norm(b))
+    hist = [float(np.linalg.norm(r)) / bnorm]
+    if hist[0] <= rtol:
+        return x, 0, hist, hist[0]
+    z = apply_prec(r)
+    p = z.copy()
+    rz = float(r @ z)
+    it = 0
+    for it in range(1, maxit + 1):
+        q = apply_a(p)
+        pq = float(p @ q)
+        if pq <= 0:
+            raise ArithmeticError("PCG breakdown: p^T A p <= 0")
+        alpha = rz / pq
+        x = x + alpha * p
+        r_old = r
+        r = r - alpha * q
+        hist.append(float(np.linalg.norm(r)) / bnorm)
+        if hist[-1] <= rtol:
+            break
+        z = apply_prec(r)
+        rz_new = float(r @ z)
+        betac = (float(z @ (r - r_old)) if flexible else rz_new) / rz
+        rz = rz_new
+        p = z + betac * p
+    true_res = float(np.linalg.norm(b - apply_a(x))) / bnorm
+    return x, it, hist, true_res
+
+
+def energy_factor(levels: list[Level], e0, k: int, tol: float = 1e-8, maxit: int = 50):
+    """Convergence factor in the energy norm (Example 5.1's protocol with b = 0):
+    iterate e <- V(0, e) until ||e||_A < tol ||e0||_A or maxit cycles, and
+    return (||e_n||_A^2 / ||e_0||_A^2)^{1/(2n)} and n."""
+    a0 = levels[0]
+    e = np.array(e0, dtype=np.float64)
+    en0 = float(e @ a0.apply_a(e))
+    zero = np.zeros_like(e)
+    n = 0
+    en = en0
+    while n < maxit:
+        e = vcycle_x(levels, zero, e, k)
+        n += 1
+        en = float(e @ a0.apply_a(e))
+        if np.sqrt(en / en0) < tol:
+            break
+    return (en / en0) ** (1.0 / (2 * n)), n

@@ -1,0 +1,204 @@
+"""Synthetic PUM-shaped block-sparse SPD matrices.
+
+Shape of the workloads (paper, Sec. 4 and Sec. 5): a patch grid of 2^l
+patches per side in d dimensions (Fig. pum_cover), one dense local block of
+size b = C(p+d, d) per patch, block couplings between overlapping patches, and
+SPD operators of biharmonic (fourth order) or triharmonic (sixth order) type.
+The PUM assembly itself is not reproduced; instead
+
+    A = R^T (D (x) I_b) R,   D = L^q,
+
+with L the unscaled Dirichlet Laplacian on the patch grid (2d on the
+diagonal, -1 for each grid neighbour), q = 2 (biharmonic-like) or 3
+(triharmonic-like), and R block-diagonal with R_i = Q_i diag(exp(u_i)),
+Q_i Haar-orthogonal and u_i ~ U[-1, 1]^b. Block (i, j) of A is
+D_ij R_i^T R_j. Blocks are numbered lexicographically with x fastest:
+i = ix + n*iy (+ n^2*iz).
+
+Random streams: SeedSequence(seed).spawn(4) gives, in order, the streams for
+Q, for u, for right-hand sides and for Lanczos start vectors.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from math import comb
+
+import numpy as np
+import scipy.sparse as sp
+
+STREAM_Q, STREAM_U, STREAM_RHS, STREAM_LANCZOS = range(4)
+
+
+def _streams(seed: int):
+    return [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(4)]
+
+
+def grid_sizes(n: int, levels: int) -> list[int]:
+    """Patches per side on each level, finest first (n, n/2, ...)."""
+    out = []
+    for _ in range(levels):
+        out.append(n)
+        n //= 2
+    return out
+
+
+def laplacian(n: int, dim: int) -> sp.csr_matrix:
+    """Unscaled Dirichlet Laplacian on an n^dim patch grid, x fastest.
+
+    Integer valued: 2*dim on the diagonal and -1 for each of the (up to)
+    2*dim grid neighbours. Exact in floating point.
+    """
+    one = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    eye = sp.identity(n, format="csr")
+    if dim == 1:
+        return one.astype(np.float64)
+    if dim == 2:
+        lap = sp.kron(eye, one) + sp.kron(one, eye)
+    elif dim == 3:
+        lap = (sp.kron(eye, sp.kron(eye, one)) + sp.kron(eye, sp.kron(one, eye))
+               + sp.kron(one, sp.kron(eye, eye)))
+    else:
+        raise ValueError("dim must be 1, 2 or 3")
+    return sp.csr_matrix(lap, dtype=np.float64)
+
+
+def stencil_matrix(n: int, dim: int, power: int) -> sp.csr_matrix:
+    """D = L^power on the patch grid, with sorted column indices."""
+    lap = laplacian(n, dim)
+    d = lap
+    for _ in range(power - 1):
+        d = d @ lap
+    d = sp.csr_matrix(d)
+    d.eliminate_zeros()
+    d.sort_indices()
+    return d
+
+
+def _haar_orthogonal(rng: np.random.Generator, count: int, b: int) -> np.ndarray:
+    """Haar-distributed orthogonal b x b matrices: QR of a Gaussian matrix
+    with the signs of R's diagonal moved into Q (Mezzadri's correction)."""
+    z = rng.standard_normal((count, b, b))
+    q, r = np.linalg.qr(z)
+    sgn = np.sign(np.einsum("kii->ki", r))
+    sgn[sgn == 0] = 1.0
+    return q * sgn[:, None, :]
+
+
+@dataclass
+class Problem:
+    """A block-sparse SPD matrix in BSR form plus the data that made it."""
+
+    n: int                 # patches per side
+    dim: int
+    b: int                 # block size
+    power: int             # D = L^power
+    seed: int
+    rowptr: np.ndarray     # int64, nb+1
+    colidx: np.ndarray     # int32, nnzb (ascending within each row)
+    vals: np.ndarray       # float64, (nnzb, b, b), each block row-major
+    dstencil: sp.csr_matrix = field(repr=False)  # the scalar D
+    rfac: np.ndarray = field(repr=False)         # (nb, b, b) block-diagonal R
+
+    @property
+    def nb(self) -> int:
+        return int(self.rowptr.shape[0] - 1)
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.colidx.shape[0])
+
+    @property
+    def ndof(self) -> int:
+        return self.nb * self.b
+
+    def to_scipy(self) -> sp.bsr_matrix:
+        return sp.bsr_matrix((self.vals, self.colidx, self.rowptr),
+                             shape=(self.ndof, self.ndof))
+
+
+def make_problem(n: int, dim: int, b: int, power: int, seed: int = 0,
+                 rotate: bool = True, chunk: int = 1 << 19) -> Problem:
+    """Build A = R^T (D (x) I_b) R on an n^dim patch grid.
+
+    With rotate=False, R = I and A = D (x) I_b (the scalar problem repeated
+    per block component).
+    """
+    dmat = stencil_matrix(n, dim, power)
+    nb = dmat.shape[0]
+    streams = _streams(seed)
+    if rotate:
+        q = _haar_orthogonal(streams[STREAM_Q], nb, b)
+        u = streams[STREAM_U].uniform(-1.0, 1.0, size=(nb, b))
+        rfac = q * np.exp(u)[:, None, :]          # Q_i diag(exp u_i)
+    else:
+        rfac = np.broadcast_to(np.eye(b), (nb, b, b)).copy()
+    rowptr = dmat.indptr.astype(np.int64)
+    colidx = dmat.indices.astype(np.int32)
+    rows = np.repeat(np.arange(nb, dtype=np.int64), np.diff(rowptr))
+    dval = dmat.data
+    vals = np.empty((colidx.shape[0], b, b), dtype=np.float64)
+    for s in range(0, colidx.shape[0], chunk):
+        e = min(s + chunk, colidx.shape[0])
+        ri = rfac[rows[s:e]]
+        rj = rfac[colidx[s:e]]
+        # D_ij * R_i^T R_j
+        np.matmul(np.swapaxes(ri, 1, 2), rj, out=vals[s:e])
+        vals[s:e] *= dval[s:e, None, None]
+    return Problem(n=n, dim=dim, b=b, power=power, seed=seed, rowptr=rowptr,
+                   colidx=colidx, vals=vals, dstencil=dmat, rfac=rfac)
+
+
+def pum_block_size(p: int, dim: int) -> int:
+    """dim V_i = C(p + d, d) for local polynomials of degree p."""
+    return comb(p + dim, dim)
+
+
+def prolongator_1d(nc: int) -> sp.csr_matrix:
+    """Cell-centred 1D prolongation from nc to 2*nc cells.
+
+    Fine cell 2I+a takes 3/4 of coarse cell I and 1/4 of its neighbour on
+    the same side (I-1 for a = 0, I+1 for a = 1); a neighbour outside the
+    grid is dropped (zero ghost value).
+    """
+    nf = 2 * nc
+    rows, cols, vals = [], [], []
+    for f in range(nf):
+        big, a = divmod(f, 2)
+        rows.append(f)
+        cols.append(big)
+        vals.append(0.75)
+        other = big - 1 if a == 0 else big + 1
+        if 0 <= other < nc:
+            rows.append(f)
+            cols.append(other)
+            vals.append(0.25)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+
+
+def prolongator(nc: int, dim: int) -> sp.csr_matrix:
+    """Tensor-product patch prolongator P_s from nc^dim to (2nc)^dim patches
+    (scalar weights; the block operator is P_s (x) I_b). x is fastest."""
+    p1 = prolongator_1d(nc)
+    p = p1
+    for _ in range(dim - 1):
+        p = sp.kron(p1, p)
+    p = sp.csr_matrix(p)
+    p.sort_indices()
+    return p
+
+
+def rhs(seed: int, ndof: int) -> np.ndarray:
+    """Right-hand side ~ N(0, 1)^ndof from the seed's RHS stream."""
+    return _streams(seed)[STREAM_RHS].standard_normal(ndof)
+
+
+def lanczos_starts(seed: int, sizes: list[int]) -> list[np.ndarray]:
+    """One N(0,1) start vector per level, drawn in level order from the
+    seed's Lanczos stream."""
+    rng = _streams(seed)[STREAM_LANCZOS]
+    return [rng.standard_normal(m) for m in sizes]
+
+
+def uniform_start(seed: int, ndof: int) -> np.ndarray:
+    """Initial error with entries in U(-1, 1) for convergence-factor runs."""
+    return np.random.default_rng(np.random.SeedSequence([seed, 7919])).uniform(-1.0, 1.0, ndof)

@@ -1,0 +1,120 @@
+"""Pins for the oracle's hierarchy: Galerkin variational identity, Lanczos
+bounds, V(k,k) symmetry, exact one-level cycle, PCG against a dense solve,
+scale invariance and a convergent energy-norm factor."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import fsai, lanczos, multilevel, solver
+from oracle.bsr import from_problem
+from problems import grid_sizes, lanczos_starts, make_problem, prolongator, rhs
+
+
+def _hier(n=16, b=3, levels=3, mode="lower", tmax=0, seed=0, scale=1.0, betas=None):
+    p = make_problem(n, 2, b, 2, seed=seed)
+    a = from_problem(p)
+    a.vals = a.vals * scale
+    sizes = grid_sizes(n, levels)
+    pro = [prolongator(sizes[l + 1], 2) for l in range(levels - 1)]
+    starts = lanczos_starts(seed, [s * s * b for s in sizes])
+    return p, solver.build_levels(a, pro, starts, mode, tmax, betas=betas)
+
+
+def test_galerkin_variational_identity():
+    p = make_problem(16, 2, 3, 2, seed=1)
+    a = from_problem(p)
+    ps = prolongator(8, 2)
+    ac = multilevel.galerkin(a, ps)
+    pb = np.kron(ps.toarray(), np.eye(3))
+    rng = np.random.default_rng(0)
+    xc, yc = rng.standard_normal((2, ac.nb * 3))
+    lhs = xc @ (ac.scipy() @ yc)
+    rhs_ = (pb @ xc) @ (a.scipy() @ (pb @ yc))
+    assert abs(lhs - rhs_) < 1e-12 * abs(rhs_)
+    # coarse block stencil: 5x5 box in the interior
+    assert max(np.diff(ac.rowptr)) == 25
+    acd = ac.dense()
+    assert abs(acd - acd.T).max() < 1e-13 * abs(acd).max()
+
+
+def test_lanczos_brackets_lambda_max():
+    p = make_problem(8, 2, 3, 2, seed=0)
+    a = from_problem(p)
+    g = fsai.fsai(a, *fsai.pattern_lower(a))
+    gd, ad = g.dense(), a.dense()
+    bm = gd @ ad @ gd.T
+    lmax = np.linalg.eigvalsh(bm).max()
+    v0 = lanczos_starts(0, [ad.shape[0]])[0]
+    beta, theta = lanczos.lmax(lambda v: bm @ v, v0, 100, 1.01)
+    assert theta <= lmax * (1 + 1e-12)
+    assert beta >= lmax
+    assert theta > 0.999 * lmax
+
+
+def test_lanczos_small_invariant_subspace():
+    # operator with 3 distinct eigenvalues: the recurrence stops early and the
+    # Ritz value is exact
+    d = np.array([1.0, 2.0, 5.0] * 10)
+    v0 = np.ones(30)
+    beta, theta = lanczos.lmax(lambda v: d * v, v0, 100, 1.0)
+    assert abs(theta - 5.0) < 1e-12
+
+
+def test_vcycle_symmetric():
+    p, levels = _hier()
+    rng = np.random.default_rng(3)
+    n = p.ndof
+    b1, b2 = rng.standard_normal((2, n))
+    v1 = multilevel.vcycle(levels, 0, b1, 3)
+    v2 = multilevel.vcycle(levels, 0, b2, 3)
+    assert abs(v1 @ b2 - b1 @ v2) < 1e-12 * abs(v1 @ b2)
+    # positive definite on random vectors
+    assert v1 @ b1 > 0 and v2 @ b2 > 0
+
+
+def test_single_level_is_exact_and_pcg_takes_one_step():
+    p = make_problem(6, 2, 3, 2, seed=0)
+    a = from_problem(p)
+    levels = solver.build_levels(a, [], [], "lower")
+    b = rhs(0, p.ndof)
+    x, it, hist, true_res = multilevel.pcg(levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, 2),
+                                           b, 1e-10, 10)
+    assert it == 1 and true_res < 1e-10
+
+
+def test_pcg_matches_dense_solve():
+    p, levels = _hier(n=16, b=3, levels=3)
+    b = rhs(0, p.ndof)
+    x, it, hist, true_res = multilevel.pcg(levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, 3),
+                                           b, 1e-10, 100)
+    xd = sla.solve(levels[0].a.dense(), b, assume_a="pos")
+    assert hist[-1] <= 1e-10
+    assert np.linalg.norm(x - xd) <= 1e-6 * np.linalg.norm(xd)
+    assert it < 40
+
+
+def test_pcg_scale_invariance():
+    # A -> alpha A leaves M A, beta and the iteration count unchanged
+    p, l1 = _hier(n=16, b=3, levels=3)
+    _, l2 = _hier(n=16, b=3, levels=3, scale=1000.0)
+    b = rhs(0, p.ndof)
+    r1 = multilevel.pcg(l1[0].apply_a, lambda r: multilevel.vcycle(l1, 0, r, 3), b, 1e-8, 100)
+    r2 = multilevel.pcg(l2[0].apply_a, lambda r: multilevel.vcycle(l2, 0, r, 3), b, 1e-8, 100)
+    assert r1[1] == r2[1]
+    assert abs(l2[0].beta - l1[0].beta) < 1e-8 * l1[0].beta
+
+
+def test_energy_factor_converges():
+    from problems import uniform_start
+    p, levels = _hier(n=16, b=3, levels=3)
+    rho, n = multilevel.energy_factor(levels, uniform_start(0, p.ndof), 3)
+    assert 0 < rho < 0.9
+
+
+def test_pcg_flexible_variant_close():
+    p, levels = _hier(n=16, b=3, levels=3)
+    b = rhs(1, p.ndof)
+    r1 = multilevel.pcg(levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, 3), b, 1e-8, 100)
+    r2 = multilevel.pcg(levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, 3), b, 1e-8, 100,
+                        flexible=True)
+    assert abs(r1[1] - r2[1]) <= 1
