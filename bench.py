@@ -1,0 +1,265 @@
+"""Benchmark: fourth-kind Chebyshev / block-FSAI smoother throughput and
+V-cycle-preconditioned PCG time to 1e-8, FP64 vs mixed, on one MI355X.
+
+Workload (default): biharmonic-like 2D, 512 x 512 patches, b = 10
+(2,621,440 dofs), A = R^T (L^2 (x) I_b) R, adaptive block-FSAI with
+t_max = 8 (Algorithm 1, tau = 1, P0 = diagonal), Chebyshev degree 4,
+6-level Galerkin V(4,4), RHS N(0,1) with seed 0. Inputs are seeded synthetic
+data generated on the host and resident in HBM before any timed region.
+
+Timed steps: one step is one smoother application (Algorithm 3, degree 4,
+x != 0) on level 0: the hot loop of every V-cycle. `value` = N * k / t_app in
+GDOF/s. The PCG solves (FP64 and mixed) and the set-up phases are timed in
+the same run and reported beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=512, help="patches per side")
+    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--tmax", type=int, default=8)
+    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-grid", type=int, default=32, help="patches per side of the oracle's timing sample")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(n, b, tmax, degree, target_s=10.0):
+    """The oracle (plain FP64 NumPy/SciPy) on a bounded sample of the same
+    workload: a smaller patch grid of the same generator, block size, adaptive
+    pattern, degree and smoother. Only the smoother applications are timed."""
+    from oracle import adaptive, chebyshev, fsai, lanczos
+    from oracle.bsr import from_problem
+    from problems import lanczos_starts, make_problem, rhs
+    p = make_problem(n, 2, b, 2, seed=0)
+    a = from_problem(p)
+    t0 = time.perf_counter()
+    prow, pcol = adaptive.adaptive_pattern(a, tmax)
+    g = fsai.fsai(a, prow, pcol)
+    asp, gsp = a.scipy(), g.scipy()
+    gtsp = gsp.T.tocsr()
+    beta, _ = lanczos.lmax(lambda v: gsp @ (asp @ (gtsp @ v)), lanczos_starts(0, [p.ndof])[0])
+    setup_s = time.perf_counter() - t0
+    bvec = rhs(0, p.ndof)
+    x = np.zeros(p.ndof)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        x = chebyshev.cheb4(lambda v: asp @ v, lambda v: gtsp @ (gsp @ v), bvec, x, beta, degree)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or reps >= 100000:
+            break
+    t_app = el / reps
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        cores = os.cpu_count()
+    threads = os.environ.get("OMP_NUM_THREADS", "unset")
+    return {
+        "value": p.ndof * degree / t_app / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{reps} oracle smoother applications (Algorithm 3, degree {degree}, SciPy BSR products, "
+                   f"single-threaded) on a {n}x{n}-patch grid of the same generator (b={b}, {p.ndof} dofs, "
+                   f"adaptive t_max={tmax}); {el:.1f} s timed; oracle set-up {setup_s:.1f} s untimed; "
+                   f"host affinity {cores} cores, OMP_NUM_THREADS={threads}"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the multi-GPU form of this path is a design note, "
+              "not part of this build (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2509_06744_amd as chf
+    from problems import grid_sizes, lanczos_starts, level_basis, make_problem, prolongator, rhs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    n, b, L, k = args.n, 10, args.levels, args.degree
+    log(f"generating {n}x{n} b={b} problem")
+    t0 = time.perf_counter()
+    p = make_problem(n, 2, b, 2, seed=0)
+    sizes = grid_sizes(n, L)
+    pro = [prolongator(sizes[l + 1], 2) for l in range(L - 1)]
+    starts = lanczos_starts(0, [s * s * b for s in sizes])
+    bvec = rhs(0, p.ndof)
+    bases = level_basis(p, L)
+    log(f"generated in {time.perf_counter() - t0:.1f} s; uploading")
+    A = chf.bsr_create(p.nb, p.b, p.rowptr, p.colidx, p.vals)
+    nnzb = p.nnzb
+    v0 = [torch.from_numpy(s).to(dev) for s in starts[:-1]]
+    bd = torch.from_numpy(bvec).to(dev)
+    del p
+
+    def build(dtype):
+        H = chf.levels_create(A)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for ps, basis in zip(pro, bases):
+            chf.levels_add_coarse(H, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
+        torch.cuda.synchronize()
+        t_gal = time.perf_counter() - t
+        t = time.perf_counter()
+        chf.levels_setup(H, degree=k, pattern=1, tmax=args.tmax, dtype=dtype, v0=v0)
+        torch.cuda.synchronize()
+        return H, {"galerkin_ms": 1e3 * t_gal, "levels_setup_ms": 1e3 * (time.perf_counter() - t)}
+
+    log("set-up FP64 hierarchy (adaptive pattern, FSAI, Lanczos, coarse inverse)")
+    H, setup64 = build(chf.F64)
+    # the level-0 pattern alone, timed
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P0 = chf.pattern_adaptive(A, args.tmax)
+    t_pat = time.perf_counter() - t
+    rp, _ = chf.pattern_export(P0)
+    nnzg = int(rp[-1])
+    t = time.perf_counter()
+    Gtmp = chf.fsai_setup(A, P0)
+    torch.cuda.synchronize()
+    t_fsai = time.perf_counter() - t
+    del Gtmp
+    setup64.update({"adaptive_pattern_level0_ms": 1e3 * t_pat, "fsai_setup_level0_ms": 1e3 * t_fsai})
+    log(f"set-up done: {setup64}")
+    _, G0, _ = chf.levels_get(H, 0)
+    beta0 = chf.levels_get_beta(H, 0)
+    N = A.info()[0] * b
+
+    # ---- timed region: K smoother applications on level 0 (x != 0)
+    stream = torch.cuda.current_stream()
+    x = torch.zeros(N, dtype=torch.float64, device=dev)
+    work = torch.zeros(3 * N, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        chf.cheb4_smooth(A, G0, beta0, k, bd, x, x_is_zero=False, work=work)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        chf.cheb4_smooth(A, G0, beta0, k, bd, x, x_is_zero=False, work=work)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms_app = e0.elapsed_time(e1) / args.steps
+    gdofs = N * k / (ms_app * 1e-3) / 1e9
+    s = 8
+    b_step = nnzb * (b * b * s + 4) + 2 * nnzg * (b * b * s + 4) + 10 * N * s
+    b_app = k * b_step
+    log(f"smoother: {ms_app:.3f} ms/application, {gdofs:.3f} GDOF/s, "
+        f"{b_app / (ms_app * 1e-3) / 1e9:.0f} GB/s algorithmic")
+
+    # ---- dominant kernel: the A residual SpMV r = b - A x, timed alone
+    r = torch.empty_like(x)
+    for _ in range(3):
+        chf.bsr_spmv(A, x, r, bvec=bd)
+    torch.cuda.synchronize()
+    reps = max(20, args.steps)
+    e0.record(stream)
+    for _ in range(reps):
+        chf.bsr_spmv(A, x, r, bvec=bd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_k1 = e0.elapsed_time(e1) / reps
+    bytes_k1 = nnzb * (b * b * 8 + 4) + 3 * N * 8
+    achieved = bytes_k1 / (ms_k1 * 1e-3) / 1e9
+    log(f"residual SpMV: {ms_k1:.4f} ms, {achieved:.0f} GB/s algorithmic")
+
+    out = {
+        "metric": "smoother GDOF/s (%HBM peak) + PCG time to 1e-8, FP64 vs mixed, 1 GPU",
+        "value": round(gdofs, 4),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_app, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"biharmonic-like 2D PUM-shaped A=R^T(L^2 (x) I_b)R, {n}x{n} patches, b={b}, "
+                         f"{N} dofs, adaptive block-FSAI t_max={args.tmax}, fourth-kind Chebyshev degree {k}, "
+                         f"{L}-level Galerkin V({k},{k}) PCG"),
+            "patches": n, "block": b, "ndof": N, "nnzb_A": nnzb, "nnzb_G": nnzg, "degree": k,
+            "tmax": args.tmax, "levels": L, "rhs": "N(0,1) seed 0",
+        },
+        "smoother": {
+            "ms_per_application": round(ms_app, 5),
+            "algorithmic_bytes_per_application": b_app,
+            "achieved_GBs": round(b_app / (ms_app * 1e-3) / 1e9, 1),
+            "hbm_frac": round(b_app / (ms_app * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "wall_s_timed_region": round(t_wall, 4),
+        },
+        "roofline": {
+            "kernel": "k_sell_spmv<10,double,double,EPI_RES> (r = b - A x, level 0)",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(ms_k1, 5), "algorithmic_bytes_per_launch": bytes_k1,
+        },
+        "setup_fp64": {kk: round(v, 2) for kk, v in setup64.items()},
+    }
+
+    # ---- PCG FP64 and mixed
+    if not args.no_pcg:
+        res = {}
+        for name, dt, flex, Hh in [("fp64", chf.F64, False, H), ("mixed_f32", chf.F32, True, None),
+                                   ("mixed_bf16g", chf.BF16, True, None)]:
+            setup = None
+            if Hh is None:
+                log(f"set-up {name} hierarchy")
+                Hh, setup = build(dt)
+            xs = torch.zeros(N, dtype=torch.float64, device=dev)
+            chf.pcg_solve(Hh, bd, xs, rtol=1e-8, maxit=200, flexible=flex)   # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            it, hist, tr, rc = chf.pcg_solve(Hh, bd, xs, rtol=1e-8, maxit=200, flexible=flex,
+                                             raise_on_noconv=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            res[name] = {"iterations": it, "time_ms": round(1e3 * el, 2), "ms_per_iteration": round(1e3 * el / max(it, 1), 3),
+                         "final_relres": float(hist[-1]), "true_relres": tr, "converged": rc == 0,
+                         "flexible_cg": flex}
+            if setup:
+                res[name]["setup"] = {kk: round(v, 2) for kk, v in setup.items()}
+            log(f"PCG {name}: {res[name]}")
+            if Hh is not H:
+                Hh.destroy()
+        res["mixed_f32_over_fp64_time"] = round(res["mixed_f32"]["time_ms"] / res["fp64"]["time_ms"], 4)
+        res["mixed_bf16g_over_fp64_time"] = round(res["mixed_bf16g"]["time_ms"] / res["fp64"]["time_ms"], 4)
+        out["pcg"] = res
+
+    if not args.no_cpu_baseline:
+        log("timing the oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_grid, b, args.tmax, k)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,203 @@
+/*
+ * chf.h -- C ABI of the MI355X (gfx950) library for fourth-kind Chebyshev
+ * smoothing with block-FSAI preconditioners inside a Galerkin V-cycle.
+ *
+ * Problem statement (paper Sec. 2, Def. 2.1 and Def. 2.2): A is symmetric
+ * positive definite with a uniform block structure of n block rows of size b;
+ * a factor pattern is lower block-triangular and contains the diagonal
+ * (Eq. lower_triangular_pattern).
+ *
+ * Conventions for every call:
+ *  - Return value: CHF_OK (0) or a negative chf_status; chf_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - Host arrays are read during the call only and never retained.
+ *  - Device vectors are caller-owned buffers on the current HIP device;
+ *    handles own their device memory and free it in the matching *_destroy.
+ *  - `stream` is the caller's HIP stream (0 = null stream). A call returns
+ *    after enqueueing work, except where a scalar must come back to the host
+ *    (PCG stop test, Lanczos, set-up calls), which synchronise `stream`.
+ *  - Block indices are 0-based; block b x b values are row-major and
+ *    contiguous; BSR column indices ascend within each row.
+ *  - Vector element types follow the operator's working dtype: CHF_F64 ->
+ *    double, CHF_F32 and CHF_BF16 (BF16 factor storage) -> float.
+ */
+#ifndef CHF_H
+#define CHF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CHF_OK = 0,
+    CHF_EINVAL = -1,      /* bad argument, malformed pattern, non-finite input */
+    CHF_ENOMEM = -2,      /* device allocation failed */
+    CHF_ENOTSPD = -3,     /* a local (or coarse) Cholesky pivot was not positive */
+    CHF_EDEVICE = -4,     /* HIP runtime error */
+    CHF_ENOCONV = -5,     /* PCG did not reach rtol within maxit */
+    CHF_EBREAKDOWN = -6   /* PCG breakdown: p^T A p <= 0 or r^T z <= 0 */
+} chf_status;
+
+typedef enum { CHF_F64 = 0, CHF_F32 = 1, CHF_BF16 = 2 } chf_dtype;
+
+typedef struct chf_bsr_s* chf_bsr;
+typedef struct chf_pattern_s* chf_pattern;
+typedef struct chf_fsai_s* chf_fsai;
+typedef struct chf_levels_s* chf_levels;
+typedef struct chf_mlp_s* chf_mlp;
+
+/* Last error message of the calling thread ("" if none). */
+const char* chf_last_error(void);
+/* Library version string. */
+const char* chf_version(void);
+
+/* ---------------------------------------------------------------- BSR ---- */
+/* Block-sparse SPD matrix with block structure B = {b,...,b} (Def. 2.1).
+ * rowptr: host int64[nb+1]; colidx: host int32[nnzb], ascending per row;
+ * vals: nnzb*b*b doubles, host or device (vals_on_device), block e at
+ * vals[e*b*b], row-major. The matrix is copied; b must be in [1, 64].
+ * EINVAL on bad structure or non-finite values. */
+int chf_bsr_create(int64_t nb, int32_t b, const int64_t* rowptr, const int32_t* colidx,
+                   const double* vals, int vals_on_device, chf_bsr* out);
+int chf_bsr_destroy(chf_bsr A);
+int chf_bsr_info(chf_bsr A, int64_t* nb, int32_t* b, int64_t* nnzb);
+/* Copy structure (host rowptr[nb+1], colidx[nnzb]) and FP64 values
+ * (host vals[nnzb*b*b]) out; any pointer may be NULL. */
+int chf_bsr_export(chf_bsr A, int64_t* rowptr, int32_t* colidx, double* vals);
+/* y = A x (residual == 0) or y = bvec - A x (residual != 0), on device
+ * vectors of `dtype` (CHF_F64: double, CHF_F32: float with FP32 storage of A). */
+int chf_bsr_spmv(chf_bsr A, chf_dtype dtype, const void* x, const void* bvec, void* y,
+                 int residual, hipStream_t stream);
+
+/* ------------------------------------------------------------ patterns ---- */
+/* Lower block triangle of A with the diagonal (static pattern, Sec. 2.1). */
+int chf_pattern_lower(chf_bsr A, chf_pattern* out);
+/* Pattern from host CSR (rowptr int64[nb+1], colidx int32[nnz]); EINVAL
+ * unless lower triangular, strictly ascending per row, diagonal present. */
+int chf_pattern_from_csr(int64_t nb, const int64_t* rowptr, const int32_t* colidx,
+                         chf_pattern* out);
+/* Adaptive block-FSAI pattern (Algorithm 1, Lemma 2.4) from P0 = diagonal,
+ * computed on the GPU. tmax >= 0 adaptive steps; tau in (0, 1]. A candidate
+ * c < k with structurally nonzero (FA)_kc enters row k when
+ * g* = -log rho_c* > -log tau + 1e-12; ties within a relative 1e-9 of g* go to
+ * the smallest column. Blocks per row are limited to tmax+1 <= 32. */
+int chf_pattern_adaptive(chf_bsr A, int tmax, double tau, chf_pattern* out);
+int chf_pattern_info(chf_pattern P, int64_t* nb, int64_t* nnz);
+int chf_pattern_export(chf_pattern P, int64_t* rowptr, int32_t* colidx);
+int chf_pattern_destroy(chf_pattern P);
+
+/* ---------------------------------------------------------------- FSAI ---- */
+/* Block-FSAI factor G = S^{-1/2} F on pattern P (Def. 2.2), with S^{-1/2}
+ * the inverse Cholesky root of S_kk. All local SPD systems A[P_k, P_k]
+ * (size b*|P_k| <= 320) are factorised in FP64 in one persistent launch.
+ * g_store: storage of G for the smoother (F64, F32 or BF16); the FP64
+ * values are kept for export and Lanczos. On ENOTSPD *bad_row (may be NULL)
+ * is the smallest block row whose local factorisation failed. */
+int chf_fsai_setup(chf_bsr A, chf_pattern P, chf_dtype g_store, chf_fsai* out,
+                   int64_t* bad_row);
+int chf_fsai_destroy(chf_fsai G);
+/* G's FP64 blocks in pattern order (host double[nnz*b*b]). */
+int chf_fsai_export(chf_fsai G, double* vals);
+/* z = G^T G r (the preconditioner M r), device vectors of dtype. work: n. */
+int chf_fsai_apply(chf_fsai G, chf_dtype dtype, const void* r, void* z, void* work,
+                   hipStream_t stream);
+
+/* Largest eigenvalue of G A G^T (= of M A) by `iters` plain Lanczos steps
+ * from the device start vector v0 (double[N], not modified); theta is the
+ * largest Ritz value and *beta = safety * theta (Sec. 5: 100 steps, 1.01).
+ * dtype selects which stored operators are used (F64, or the rounded F32/BF16
+ * ones, evaluated in FP64 arithmetic). Synchronises `stream`. */
+int chf_lmax_lanczos(chf_bsr A, chf_fsai G, chf_dtype dtype, int iters, const double* v0,
+                     double safety, double* beta, double* theta, hipStream_t stream);
+
+/* ---------------------------------------------------------- smoother ---- */
+/* Algorithm 3 (Chebyshev iteration of the fourth kind), degree >= 1, with
+ * M = G^T G and beta >= lambda_max(MA). b, x: device vectors (N = nb*b) of
+ * dtype; x is updated in place (x_is_zero: x's input is ignored and taken as
+ * 0, saving one product with A). work: device buffer of 3N elements. */
+int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree,
+                     const void* b, void* x, int x_is_zero, void* work, hipStream_t stream);
+
+/* ----------------------------------------------------------- V-cycle ---- */
+typedef struct {
+    int degree;          /* Chebyshev degree k of V(k,k) */
+    int pattern;         /* 0: lower(A_l), 1: adaptive (Algorithm 1), 2: diagonal */
+    int tmax;            /* adaptive steps */
+    double tau;          /* adaptive threshold (1.0 in the paper) */
+    int lanczos_iters;   /* 100 in the paper */
+    double safety;       /* 1.01 in the paper */
+    chf_dtype dtype;     /* F64: plain; F32: A_l, G_l FP32; BF16: A_l FP32, G_l BF16 */
+} chf_level_opts;
+
+/* Empty hierarchy whose finest operator is A0 (borrowed: A0 must outlive L). */
+int chf_levels_create(chf_bsr A0, chf_levels* out);
+/* Append a coarser level (Sec. 5: Galerkin coarse operators A_c = P^T A P).
+ * The prolongation is P = T (P_s (x) I_b): p_* is the scalar patch
+ * prolongation P_s (host CSR, nf x nc, nf = current coarsest block count) and
+ * `basis` (host double[nf*b*b], may be NULL for T = I) the block-diagonal
+ * change from the interpolated local bases to the fine level's local bases.
+ * The Galerkin product is formed on the GPU. */
+int chf_levels_add_coarse(chf_levels L, int64_t nc, const int64_t* p_rowptr,
+                          const int32_t* p_colidx, const double* p_vals, const double* basis);
+/* Per level except the coarsest: pattern, G (FSAI), beta (Lanczos from
+ * v0[l], device double[N_l]); coarsest: dense FP64 Cholesky-based inverse.
+ * v0 may be NULL only if every beta is set afterwards with
+ * chf_levels_set_beta. On ENOTSPD *bad_row is set as in chf_fsai_setup
+ * (the coarsest level reports -2). */
+int chf_levels_setup(chf_levels L, const chf_level_opts* opts, const double* const* v0,
+                     int64_t* bad_row);
+int chf_levels_destroy(chf_levels L);
+int chf_levels_info(chf_levels L, int* nlevels, int64_t* nb_per_level /* [nlevels] or NULL */);
+/* Borrowed handles of level l (valid while L lives; G is NULL on the coarsest). */
+int chf_levels_get(chf_levels L, int level, chf_bsr* A, chf_fsai* G, chf_pattern* P);
+int chf_levels_get_beta(chf_levels L, int level, double* beta);
+int chf_levels_set_beta(chf_levels L, int level, double beta);
+/* One V(k,k) cycle on level 0: x <- V(b, x); vectors of the hierarchy's
+ * working dtype (double for F64, float otherwise). */
+int chf_vcycle(chf_levels L, const void* b, void* x, int x_is_zero, hipStream_t stream);
+/* FP64 PCG from x = 0 with one V(k,k) cycle as preconditioner (cast to and
+ * from the working dtype for mixed hierarchies). Stops when the recursive
+ * residual ||r|| <= rtol ||b||. flexible != 0: Polak-Ribiere beta.
+ * relres_hist (host, maxit+1, may be NULL) receives ||r_i||/||b||;
+ * true_relres (may be NULL) receives ||b - A x|| / ||b|| in FP64.
+ * ENOCONV if maxit is reached (x holds the last iterate). */
+int chf_pcg_solve(chf_levels L, const double* b, double* x, double rtol, int maxit,
+                  int flexible, int* iters, double* relres_hist, double* true_relres,
+                  hipStream_t stream);
+
+/* ------------------------------------------------------- learned pattern -- */
+/* Candidate features for the learned pattern proposer: for each block row k
+ * and each candidate c in the strictly lower part of the row pattern of A^2,
+ * 4 FP32 features: ||A_kc||_F, ||A_cc^{-1} A_ck||_F, patch distance |k - c|
+ * measured on the grid given by (nx, ny) (nz implied), and the one-step gain
+ * -log rho_c at P = {k} (Lemma 2.4). Features are written to a device buffer
+ * (float[ncand*4]); the candidate CSR (host int64 rowptr[nb+1], int32
+ * cols[ncand]) is returned through chf_mlp_candidates. */
+int chf_mlp_candidates(chf_bsr A, int64_t* ncand, int64_t* rowptr, int32_t* cols);
+int chf_mlp_features(chf_bsr A, int32_t nx, int32_t ny, float* feats, hipStream_t stream);
+/* 4 -> 64 -> 64 -> 1 MLP with ReLU, FP32 parameters (4545 floats, layout
+ * W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3) and Adam moments. */
+int chf_mlp_create(const float* params_host, chf_mlp* out);
+int chf_mlp_destroy(chf_mlp net);
+int chf_mlp_get_params(chf_mlp net, float* params_host);
+/* Logits for n feature rows (device float[n*4] -> float[n]). */
+int chf_mlp_forward(chf_mlp net, const float* feats, int64_t n, float* logits, hipStream_t stream);
+/* Mean binary cross-entropy-with-logits loss and its gradient (device
+ * float[4545] written to grad) over n rows with labels in {0, 1}. */
+int chf_mlp_loss_grad(chf_mlp net, const float* feats, const float* labels, int64_t n,
+                      float* loss_host, float* grad, hipStream_t stream);
+/* One Adam step (lr, beta1, beta2, eps) on the mini-batch. */
+int chf_mlp_train_step(chf_mlp net, const float* feats, const float* labels, int64_t n,
+                       float lr, float beta1, float beta2, float eps, float* loss_host,
+                       hipStream_t stream);
+/* Pattern from the t highest-scoring candidates per row (ties to the smaller
+ * column), diagonal added. */
+int chf_mlp_propose(chf_bsr A, chf_mlp net, int32_t nx, int32_t ny, int t, chf_pattern* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHF_H */

@@ -20,9 +20,17 @@ from . import chebyshev
 from .bsr import Bsr, from_scipy
 
 
-def galerkin(a: Bsr, p_s: sp.csr_matrix) -> Bsr:
-    """A_c = P^T A P with P = P_s (x) I_b."""
-    pb = sp.csr_matrix(sp.kron(p_s, sp.identity(a.b), format="csr"))
+def block_prolongator(p_s: sp.csr_matrix, b: int, basis=None) -> sp.csr_matrix:
+    """P = T (P_s (x) I_b) with T block diagonal (identity when basis is None)."""
+    pb = sp.csr_matrix(sp.kron(p_s, sp.identity(b), format="csr"))
+    if basis is not None:
+        pb = sp.csr_matrix(sp.block_diag(list(basis), format="csr") @ pb)
+    return pb
+
+
+def galerkin(a: Bsr, p_s: sp.csr_matrix, basis=None) -> Bsr:
+    """A_c = P^T A P with P = T (P_s (x) I_b)."""
+    pb = block_prolongator(p_s, a.b, basis)
     ac = pb.T @ a.scipy().tocsr() @ pb
     ac = sp.csr_matrix(ac)
     ac.sort_indices()
@@ -35,6 +43,7 @@ class Level:
     g: Bsr | None = None          # block-FSAI factor (None on the coarsest level)
     beta: float = 0.0
     p_s: sp.csr_matrix | None = None   # prolongation from level l+1 to level l
+    basis: np.ndarray | None = None    # block-diagonal T of P = T (P_s (x) I_b)
     chol: tuple | None = None
     a_sp: sp.bsr_matrix = field(default=None, repr=False)
     g_sp: sp.bsr_matrix = field(default=None, repr=False)
@@ -47,7 +56,7 @@ class Level:
             self.g_sp = self.g.scipy()
             self.gt_sp = self.g_sp.T.tobsr(blocksize=(self.a.b, self.a.b))
         if self.p_s is not None:
-            self.pb = sp.csr_matrix(sp.kron(self.p_s, sp.identity(self.a.b), format="csr"))
+            self.pb = block_prolongator(self.p_s, self.a.b, self.basis)
         return self
 
     def apply_a(self, v):

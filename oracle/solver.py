@@ -21,8 +21,9 @@ def make_pattern(a: Bsr, mode: str, tmax: int = 0, tau: float = 1.0):
 
 def build_levels(a0: Bsr, prolongators, starts, mode: str, tmax: int = 0,
                  tau: float = 1.0, iters: int = 100, safety: float = 1.01,
-                 patterns=None, betas=None):
-    """prolongators[l] maps level l+1 to level l (scalar patch weights);
+                 patterns=None, betas=None, bases=None):
+    """prolongators[l] maps level l+1 to level l (scalar patch weights, with
+    the block-diagonal basis change bases[l] when given: P = T (P_s (x) I));
     starts[l] is the Lanczos start vector of level l. ``patterns``/``betas``
     may fix the per-level pattern or bound instead of computing them."""
     levels = []
@@ -34,13 +35,14 @@ def build_levels(a0: Bsr, prolongators, starts, mode: str, tmax: int = 0,
             prow, pcol = patterns[l] if patterns is not None else make_pattern(a, mode, tmax, tau)
             lev.g = fsai.fsai(a, prow, pcol)
             lev.p_s = prolongators[l]
+            lev.basis = bases[l] if bases is not None else None
             lev.finish()
             if betas is not None:
                 lev.beta = betas[l]
             else:
                 op = lambda v, lv=lev: lv.g_sp @ (lv.a_sp @ (lv.gt_sp @ v))
                 lev.beta, _ = lanczos.lmax(op, np.asarray(starts[l]), iters, safety)
-            a = galerkin(a, prolongators[l])
+            a = galerkin(a, prolongators[l], lev.basis)
         else:
             lev.finish()
             lev.chol = coarse_factor(a)

@@ -1,0 +1,333 @@
+// Block-sparse matrices: creation, the slice-interleaved SpMV layout and the
+// SpMV kernels with their fused epilogues (residual, fourth-kind Chebyshev
+// update of Algorithm 3).
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+#include "kernels_common.h"
+
+namespace chf {
+
+// ---------------------------------------------------------------- layout --
+SellPlan sell_plan(int64_t nb, int b, const std::vector<int64_t>& rowptr,
+                   const std::vector<int32_t>& colidx, const std::vector<int64_t>* srcmap) {
+    SellPlan p;
+    p.nb = nb;
+    p.b = b;
+    p.S = std::max(1, 64 / b);
+    p.L = p.S * b;
+    p.nslices = (nb + p.S - 1) / p.S;
+    p.slice_off.assign(p.nslices + 1, 0);
+    for (int64_t s = 0; s < p.nslices; ++s) {
+        int64_t w = 0;
+        for (int64_t r = s * p.S; r < std::min<int64_t>(nb, (s + 1) * p.S); ++r)
+            w = std::max<int64_t>(w, rowptr[r + 1] - rowptr[r]);
+        CHF_CHECK(p.slice_off[s] + w < (1ll << 31), CHF_EINVAL, "matrix too large for the SpMV layout");
+        p.slice_off[s + 1] = (int)(p.slice_off[s] + w);
+    }
+    p.nslots = p.slice_off[p.nslices];
+    CHF_CHECK(p.nslots * (int64_t)p.S < (1ll << 31), CHF_EINVAL, "matrix too large for the SpMV layout");
+    p.cols.assign(p.nslots * p.S, 0);
+    p.src.assign(p.nslots * p.S, -1);
+    for (int64_t s = 0; s < p.nslices; ++s) {
+        int64_t off = p.slice_off[s], w = p.slice_off[s + 1] - off;
+        for (int lr = 0; lr < p.S; ++lr) {
+            int64_t row = s * p.S + lr;
+            for (int64_t j = 0; j < w; ++j) {
+                int64_t e = (off + j) * p.S + lr;
+                if (row < nb && j < rowptr[row + 1] - rowptr[row]) {
+                    int64_t idx = rowptr[row] + j;
+                    p.cols[e] = colidx[idx];
+                    p.src[e] = srcmap ? (*srcmap)[idx] : idx;
+                } else {
+                    p.cols[e] = row < nb ? (int)row : 0;
+                    p.src[e] = -1;
+                }
+            }
+        }
+    }
+    return p;
+}
+
+template <typename T>
+__global__ void k_sell_pack(int64_t total, int b, int S, int L, const int64_t* __restrict__ src,
+                            const double* __restrict__ blocks, int transpose, T* __restrict__ out) {
+    const int64_t bl = (int64_t)b * L;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        int64_t slot = e / bl;
+        int64_t rem = e - slot * bl;
+        int c = (int)(rem / L);
+        int lane = (int)(rem - (int64_t)c * L);
+        int lr = lane / b, r = lane - lr * b;
+        int64_t sb = src[slot * S + lr];
+        double v = 0.0;
+        if (sb >= 0) {
+            const double* blk = blocks + sb * b * b;
+            v = transpose ? blk[c * b + r] : blk[r * b + c];
+        }
+        store_from_f64<T>(out + e, v);
+    }
+}
+
+void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, bool transpose,
+                chf_dtype dtype, hipStream_t s) {
+    out.nb = plan.nb;
+    out.b = plan.b;
+    out.S = plan.S;
+    out.L = plan.L;
+    out.nslices = plan.nslices;
+    out.nslots = plan.nslots;
+    out.dtype = dtype;
+    out.slice_off.alloc(plan.slice_off.size());
+    out.slice_off.upload(plan.slice_off.data(), plan.slice_off.size(), s);
+    out.cols.alloc(std::max<size_t>(1, plan.cols.size()));
+    out.cols.upload(plan.cols.data(), plan.cols.size(), s);
+    DevBuf<int64_t> src(std::max<size_t>(1, plan.src.size()));
+    src.upload(plan.src.data(), plan.src.size(), s);
+    int64_t total = plan.nslots * plan.b * plan.L;
+    out.vals.alloc(std::max<int64_t>(1, total) * dtype_size(dtype));
+    if (total > 0) {
+        int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
+        if (dtype == CHF_F64)
+            hipLaunchKernelGGL((k_sell_pack<double>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
+                               src.p, d_src_blocks, (int)transpose, (double*)out.vals.p);
+        else if (dtype == CHF_F32)
+            hipLaunchKernelGGL((k_sell_pack<float>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
+                               src.p, d_src_blocks, (int)transpose, (float*)out.vals.p);
+        else
+            hipLaunchKernelGGL((k_sell_pack<bf16_t>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
+                               src.p, d_src_blocks, (int)transpose, (bf16_t*)out.vals.p);
+        CHF_LAUNCH_CHECK();
+    }
+    // src is freed at scope exit; make sure the pack has consumed it.
+    CHF_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ SpMV --
+// One 64-wide wavefront per slice; lane = local_row * b + r owns output
+// scalar r of block row slice*S + local_row and accumulates
+// sum_j sum_c block_j[r][c] * x[col_j * b + c] in TV precision. Each
+// matrix load instruction reads L contiguous elements.
+template <int BT, typename TA, typename TV, int EPI>
+__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, int brt,
+                                                   const int* __restrict__ soff, const int* __restrict__ cols,
+                                                   const TA* __restrict__ vals, const TV* __restrict__ x,
+                                                   TV* __restrict__ y, const TV* __restrict__ bv,
+                                                   TV* __restrict__ p, TV* __restrict__ xo, TV alpha, TV beta) {
+    const int b = BT ? BT : brt;
+    const int S = 64 / b;
+    const int L = S * b;
+    const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slice >= nslices || lane >= L) return;
+    const int lr = lane / b;
+    const int r = lane - lr * b;
+    const int64_t row = slice * S + lr;
+    if (row >= nb) return;
+    const int j0 = soff[slice], j1 = soff[slice + 1];
+    TV acc = 0;
+    for (int j = j0; j < j1; ++j) {
+        const int col = cols[(int64_t)j * S + lr];
+        const TA* v = vals + (int64_t)j * b * L + lane;
+        const TV* xc = x + (int64_t)col * b;
+        if constexpr (BT > 0) {
+#pragma unroll
+            for (int c = 0; c < BT; ++c) acc += load_as<TV>(v + c * L) * xc[c];
+        } else {
+            for (int c = 0; c < b; ++c) acc += load_as<TV>(v + c * L) * xc[c];
+        }
+    }
+    const int64_t o = row * b + r;
+    if constexpr (EPI == EPI_AX) {
+        y[o] = acc;
+    } else if constexpr (EPI == EPI_RES) {
+        y[o] = bv[o] - acc;
+    } else if constexpr (EPI == EPI_CHEB_FIRST0) {
+        p[o] = acc;
+        xo[o] = beta * acc;
+    } else if constexpr (EPI == EPI_CHEB_FIRST) {
+        p[o] = acc;
+        xo[o] += beta * acc;
+    } else {
+        const TV pn = alpha * p[o] + acc;
+        p[o] = pn;
+        xo[o] += beta * pn;
+    }
+}
+
+template <int BT, typename TA, typename TV>
+static void launch_spmv_t(const Sell& A, const void* x, void* y, const void* bv, int epi, void* p, void* xo,
+                          double alpha, double beta, hipStream_t s) {
+    dim3 grid((unsigned)((A.nslices + 3) / 4)), block(256);
+    if (grid.x == 0) return;
+    auto args = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, block, 0, s, A.nslices, A.nb, A.b, A.slice_off.p, A.cols.p,
+                           (const TA*)A.vals.p, (const TV*)x, (TV*)y, (const TV*)bv, (TV*)p, (TV*)xo, (TV)alpha,
+                           (TV)beta);
+    };
+    switch (epi) {
+        case EPI_AX: args(k_sell_spmv<BT, TA, TV, EPI_AX>); break;
+        case EPI_RES: args(k_sell_spmv<BT, TA, TV, EPI_RES>); break;
+        case EPI_CHEB_FIRST0: args(k_sell_spmv<BT, TA, TV, EPI_CHEB_FIRST0>); break;
+        case EPI_CHEB_FIRST: args(k_sell_spmv<BT, TA, TV, EPI_CHEB_FIRST>); break;
+        default: args(k_sell_spmv<BT, TA, TV, EPI_CHEB>); break;
+    }
+    CHF_LAUNCH_CHECK();
+}
+
+template <typename TA, typename TV>
+static void launch_spmv_b(const Sell& A, const void* x, void* y, const void* bv, int epi, void* p, void* xo,
+                          double alpha, double beta, hipStream_t s) {
+    switch (A.b) {
+        case 10: launch_spmv_t<10, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+        case 21: launch_spmv_t<21, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+        default: launch_spmv_t<0, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+    }
+}
+
+void sell_spmv(const Sell& A, chf_dtype vec, const void* x, void* y, const void* bvec, int epi, void* p,
+               void* xo, double alpha, double beta, hipStream_t s) {
+    if (A.dtype == CHF_F64) {
+        CHF_CHECK(vec == CHF_F64, CHF_EINVAL, "FP64 operator needs FP64 vectors");
+        launch_spmv_b<double, double>(A, x, y, bvec, epi, p, xo, alpha, beta, s);
+    } else if (A.dtype == CHF_F32) {
+        if (vec == CHF_F64)
+            launch_spmv_b<float, double>(A, x, y, bvec, epi, p, xo, alpha, beta, s);
+        else
+            launch_spmv_b<float, float>(A, x, y, bvec, epi, p, xo, alpha, beta, s);
+    } else {
+        if (vec == CHF_F64)
+            launch_spmv_b<bf16_t, double>(A, x, y, bvec, epi, p, xo, alpha, beta, s);
+        else
+            launch_spmv_b<bf16_t, float>(A, x, y, bvec, epi, p, xo, alpha, beta, s);
+    }
+}
+
+// ------------------------------------------------------ finiteness check --
+__global__ __launch_bounds__(256) void k_nonfinite_partial(const double* __restrict__ v, int64_t n,
+                                                           double* __restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        acc += isfinite(v[i]) ? 0.0 : 1.0;
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+__global__ void k_sum_partials_ext(const double* __restrict__ part, int np, double* __restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double a = 0;
+        for (int i = 0; i < np; ++i) a += part[i];
+        out[0] = a;
+    }
+}
+
+static int64_t count_nonfinite(const double* d, int64_t n, hipStream_t s) {
+    if (n == 0) return 0;
+    DevBuf<double> part(RED_BLOCKS + 1);
+    hipLaunchKernelGGL(k_nonfinite_partial, dim3(RED_BLOCKS), dim3(256), 0, s, d, n, part.p);
+    CHF_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sum_partials_ext, dim3(1), dim3(64), 0, s, part.p, RED_BLOCKS, part.p + RED_BLOCKS);
+    CHF_LAUNCH_CHECK();
+    double h = 0;
+    CHF_HIP(hipMemcpyAsync(&h, part.p + RED_BLOCKS, 8, hipMemcpyDeviceToHost, s));
+    CHF_HIP(hipStreamSynchronize(s));
+    return (int64_t)h;
+}
+
+}  // namespace chf
+
+using namespace chf;
+
+const Sell& chf_bsr_s::sell(chf_dtype t, hipStream_t s) {
+    if (t == CHF_F64) return sell64;
+    if (sell32.nslices == 0 && nb > 0) sell_build(sell32, plan, d_vals.p, false, CHF_F32, s);
+    return sell32;
+}
+
+extern "C" int chf_bsr_create(int64_t nb, int32_t b, const int64_t* rowptr, const int32_t* colidx,
+                              const double* vals, int vals_on_device, chf_bsr* out) {
+    return guarded([&] {
+        CHF_CHECK(out, CHF_EINVAL, "out is NULL");
+        *out = nullptr;
+        CHF_CHECK(nb >= 0 && b >= 1 && b <= 64, CHF_EINVAL, "need nb >= 0 and 1 <= b <= 64");
+        CHF_CHECK(rowptr && (nb == 0 || (colidx && vals)), CHF_EINVAL, "NULL array");
+        CHF_CHECK(rowptr[0] == 0, CHF_EINVAL, "rowptr[0] must be 0");
+        int64_t nnzb = rowptr[nb];
+        CHF_CHECK(nnzb >= 0 && nnzb < (1ll << 31), CHF_EINVAL, "bad nnzb");
+        for (int64_t i = 0; i < nb; ++i) {
+            CHF_CHECK(rowptr[i + 1] >= rowptr[i], CHF_EINVAL, "rowptr not monotone");
+            for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+                CHF_CHECK(colidx[e] >= 0 && colidx[e] < nb, CHF_EINVAL, "column index out of range");
+                CHF_CHECK(e == rowptr[i] || colidx[e] > colidx[e - 1], CHF_EINVAL,
+                          "column indices must ascend strictly within a row");
+            }
+        }
+        std::unique_ptr<chf_bsr_s> A(new chf_bsr_s);
+        A->nb = nb;
+        A->b = b;
+        A->nnzb = nnzb;
+        A->rowptr.assign(rowptr, rowptr + nb + 1);
+        A->colidx.assign(colidx, colidx + nnzb);
+        std::vector<int> rp32(nb + 1);
+        for (int64_t i = 0; i <= nb; ++i) rp32[i] = (int)rowptr[i];
+        hipStream_t s = 0;
+        A->d_rowptr.alloc(nb + 1);
+        A->d_rowptr.upload(rp32.data(), nb + 1, s);
+        A->d_colidx.alloc(std::max<int64_t>(1, nnzb));
+        A->d_colidx.upload(colidx, nnzb, s);
+        size_t nv = (size_t)nnzb * b * b;
+        A->d_vals.alloc(std::max<size_t>(1, nv));
+        if (nv) {
+            CHF_HIP(hipMemcpyAsync(A->d_vals.p, vals, nv * 8,
+                                   vals_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+        }
+        CHF_CHECK(count_nonfinite(A->d_vals.p, (int64_t)nv, s) == 0, CHF_EINVAL, "non-finite matrix value");
+        A->plan = sell_plan(nb, b, A->rowptr, A->colidx, nullptr);
+        sell_build(A->sell64, A->plan, A->d_vals.p, false, CHF_F64, s);
+        CHF_HIP(hipStreamSynchronize(s));
+        *out = A.release();
+    });
+}
+
+extern "C" int chf_bsr_destroy(chf_bsr A) {
+    return guarded([&] { delete A; });
+}
+
+extern "C" int chf_bsr_info(chf_bsr A, int64_t* nb, int32_t* b, int64_t* nnzb) {
+    return guarded([&] {
+        CHF_CHECK(A, CHF_EINVAL, "NULL handle");
+        if (nb) *nb = A->nb;
+        if (b) *b = A->b;
+        if (nnzb) *nnzb = A->nnzb;
+    });
+}
+
+extern "C" int chf_bsr_export(chf_bsr A, int64_t* rowptr, int32_t* colidx, double* vals) {
+    return guarded([&] {
+        CHF_CHECK(A, CHF_EINVAL, "NULL handle");
+        if (rowptr) std::memcpy(rowptr, A->rowptr.data(), (A->nb + 1) * 8);
+        if (colidx) std::memcpy(colidx, A->colidx.data(), A->nnzb * 4);
+        if (vals) {
+            A->d_vals.download(vals, (size_t)A->nnzb * A->b * A->b, 0);
+            CHF_HIP(hipStreamSynchronize(0));
+        }
+    });
+}
+
+extern "C" int chf_bsr_spmv(chf_bsr A, chf_dtype dtype, const void* x, const void* bvec, void* y,
+                            int residual, hipStream_t stream) {
+    return guarded([&] {
+        CHF_CHECK(A && x && y, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(!residual || bvec, CHF_EINVAL, "residual needs bvec");
+        CHF_CHECK(dtype == CHF_F64 || dtype == CHF_F32, CHF_EINVAL, "vector dtype must be F64 or F32");
+        const Sell& S = A->sell(dtype, stream);
+        sell_spmv(S, dtype, x, y, bvec, residual ? EPI_RES : EPI_AX, nullptr, nullptr, 0, 0, stream);
+    });
+}

@@ -1,0 +1,571 @@
+// Static patterns and the batched block-FSAI set-up (Def. 2.2): one dense SPD
+// system A[P_k, P_k] per block row k, all rows in one persistent launch.
+//
+// With the row's blocks ordered as P~_k ascending followed by k, the
+// Cholesky factor L of K = A[P_k, P_k] has as its last block row
+// [L_kP, L_kk] with L_kk L_kk^T = S_kk (Eq. schur_complement_fsai) and
+// L_kP L_PP^{-1} = -F[k, P~_k] (Eq. fsai_f_definition). The last b rows of
+// L^{-1} are therefore [L_kk^{-1} F_kP, L_kk^{-1}] = J F with J = L_kk^{-1}:
+// the factor G = S^{-1/2} F with the inverse Cholesky root as S^{-1/2}.
+// They are obtained from L^T Z = E (E the last b columns of I), G_k = Z^T.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+
+#include "internal.h"
+#include "kernels_common.h"
+
+namespace chf {
+
+constexpr int FSAI_MAXM = 32;    // blocks per pattern row
+constexpr int FSAI_MAXN = 320;   // local system size b * |P_k|
+
+__device__ inline int64_t tri(int64_t i) { return i * (i + 1) / 2; }
+
+// Per-row work of the set-up kernel. K: packed lower triangle (row-major),
+// Z: n x b right-hand sides; both either in LDS or in a global scratch slot.
+template <int NT>
+__device__ void fsai_row(int64_t k, int b, const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
+                         const double* __restrict__ a_vals, const int64_t* __restrict__ p_rowptr,
+                         const int* __restrict__ p_col, double* __restrict__ g_vals, double* K, double* Z,
+                         int* idx, double* sh_scal, int* sh_flag, int* bad_row) {
+    const int tid = threadIdx.x;
+    const int64_t p0 = p_rowptr[k];
+    const int m = (int)(p_rowptr[k + 1] - p0);
+    const int n = m * b;
+    const int* cols = p_col + p0;
+    // block lookup table idx[a * m + c] (a >= c): position of A[P_a, P_c] or -1
+    for (int t = tid; t < m * m; t += NT) {
+        int a = t / m, c = t - a * m;
+        int e = -1;
+        if (c <= a) {
+            int row = cols[a], want = cols[c];
+            int lo = a_rowptr[row], hi = a_rowptr[row + 1];
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                int v = a_col[mid];
+                if (v < want) lo = mid + 1; else hi = mid;
+            }
+            if (lo < a_rowptr[row + 1] && a_col[lo] == want) e = lo;
+        }
+        idx[t] = e;
+    }
+    __syncthreads();
+    // gather K = A[P_k, P_k] (lower triangle)
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t t = tid; t < nn; t += NT) {
+        int i = (int)(t / n), j = (int)(t - (int64_t)i * n);
+        if (j > i) continue;
+        int a = i / b, ra = i - a * b, c = j / b, rc = j - c * b;
+        int e = idx[a * m + c];
+        K[tri(i) + j] = e >= 0 ? a_vals[(int64_t)e * b * b + ra * b + rc] : 0.0;
+    }
+    if (tid == 0) sh_flag[0] = 1;
+    __syncthreads();
+    // right-looking Cholesky, one column at a time
+    for (int q = 0; q < n; ++q) {
+        if (tid == 0) {
+            double d = K[tri(q) + q];
+            if (!(d > 0.0) || !isfinite(d)) {
+                sh_flag[0] = 0;
+            } else {
+                double l = sqrt(d);
+                K[tri(q) + q] = l;
+                sh_scal[0] = 1.0 / l;
+            }
+        }
+        __syncthreads();
+        if (!sh_flag[0]) break;
+        const double inv = sh_scal[0];
+        for (int i = q + 1 + tid; i < n; i += NT) K[tri(i) + q] *= inv;
+        __syncthreads();
+        for (int i = q + 1 + tid; i < n; i += NT) {
+            const double liq = K[tri(i) + q];
+            double* ki = K + tri(i);
+            for (int j = q + 1; j <= i; ++j) ki[j] -= liq * K[tri(j) + q];
+        }
+        __syncthreads();
+    }
+    const bool ok = sh_flag[0] != 0;
+    __syncthreads();
+    if (!ok) {
+        if (tid == 0) atomicMin(bad_row, (int)k);
+        for (int64_t t = tid; t < (int64_t)m * b * b; t += NT) g_vals[p0 * b * b + t] = 0.0;
+        __syncthreads();
+        return;
+    }
+    // back substitution L^T Z = E_last (right-looking over rows of Z)
+    for (int64_t t = tid; t < (int64_t)n * b; t += NT) {
+        int i = (int)(t / b), c = (int)(t - (int64_t)i * b);
+        Z[t] = (i == n - b + c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int q = n - 1; q >= 0; --q) {
+        const double lqq = K[tri(q) + q];
+        if (tid < b) Z[(int64_t)q * b + tid] /= lqq;
+        __syncthreads();
+        const double* lrow = K + tri(q);
+        for (int t = tid; t < q * b; t += NT) {
+            int pidx = t / b, c = t - pidx * b;
+            Z[t] -= lrow[pidx] * Z[(int64_t)q * b + c];
+        }
+        __syncthreads();
+    }
+    // G[k, P_k] = Z^T, block a of the row = Z[a*b:(a+1)*b, :]^T
+    for (int64_t t = tid; t < (int64_t)m * b * b; t += NT) {
+        int a = (int)(t / (b * b));
+        int rem = (int)(t - (int64_t)a * b * b);
+        int r = rem / b, c = rem - r * b;
+        g_vals[(p0 + a) * b * b + rem] = Z[(int64_t)(a * b + c) * b + r];
+    }
+    __syncthreads();
+}
+
+// Persistent kernel: each workgroup pops rows (ordered by decreasing local
+// size) from a global counter until the queue is empty. Rows with n <= nlds
+// work in LDS, larger rows in the workgroup's slot of a global scratch area.
+template <int NT>
+__global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t* __restrict__ order, int b,
+                                                   const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
+                                                   const double* __restrict__ a_vals,
+                                                   const int64_t* __restrict__ p_rowptr, const int* __restrict__ p_col,
+                                                   double* __restrict__ g_vals, int nlds, double* scratch,
+                                                   int64_t scratch_stride, int* counter, int* bad_row) {
+    extern __shared__ double lds[];
+    __shared__ int idx[FSAI_MAXM * FSAI_MAXM];
+    __shared__ double sh_scal[1];
+    __shared__ int sh_flag[1];
+    __shared__ int sh_next;
+    double* lds_K = lds;
+    double* lds_Z = lds + (int64_t)nlds * (nlds + 1) / 2;
+    double* gK = scratch + (int64_t)blockIdx.x * scratch_stride;
+    double* gZ = gK + (int64_t)FSAI_MAXN * (FSAI_MAXN + 1) / 2;
+    for (;;) {
+        if (threadIdx.x == 0) sh_next = atomicAdd(counter, 1);
+        __syncthreads();
+        const int64_t it = sh_next;
+        __syncthreads();
+        if (it >= nrows) break;
+        const int64_t k = order[it];
+        const int n = (int)(p_rowptr[k + 1] - p_rowptr[k]) * b;
+        if (n <= nlds)
+            fsai_row<NT>(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, lds_K, lds_Z, idx, sh_scal,
+                         sh_flag, bad_row);
+        else
+            fsai_row<NT>(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, gK, gZ, idx, sh_scal, sh_flag,
+                         bad_row);
+    }
+}
+
+// ------------------------------------------------------------ autotuning --
+// The workgroup width (64, 128 or 256 lanes) is chosen per (b, largest local
+// size) by timing the persistent kernel on a sample of the rows; the choice is
+// cached for the process.
+struct TuneKey {
+    int b, nmax;
+    bool operator<(const TuneKey& o) const { return b != o.b ? b < o.b : nmax < o.nmax; }
+};
+static std::map<TuneKey, int> g_tuned;
+static std::mutex g_tune_mu;
+
+struct SetupArgs {
+    int64_t nrows;
+    const int64_t* order;
+    int b;
+    const int* a_rowptr;
+    const int* a_col;
+    const double* a_vals;
+    const int64_t* p_rowptr;
+    const int* p_col;
+    double* g_vals;
+    int nlds;
+    int* counter;
+    int* bad_row;
+    int nmax;
+};
+
+static size_t lds_bytes(int nlds, int b) {
+    return ((size_t)nlds * (nlds + 1) / 2 + (size_t)nlds * b) * sizeof(double);
+}
+
+static void launch_setup(int nt, const SetupArgs& a, hipStream_t s) {
+    const int cus = device_cu_count();
+    size_t shm = lds_bytes(a.nlds, a.b);
+    int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (160 * 1024) / (shm + 4096 + 64)));
+    int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(1, a.nrows));
+    int64_t stride = (int64_t)FSAI_MAXN * (FSAI_MAXN + 1) / 2 + (int64_t)FSAI_MAXN * a.b;
+    // global scratch only when some row exceeds the LDS limit
+    DevBuf<double> scratch;
+    scratch.alloc(1);
+    double* scr = scratch.p;
+    if (a.nmax > a.nlds) {
+        scratch.alloc((size_t)grid * stride);
+        scr = scratch.p;
+    }
+    fill_zero(a.counter, sizeof(int), s);
+    switch (nt) {
+        case 64:
+            hipLaunchKernelGGL(k_fsai_setup<64>, dim3(grid), dim3(64), shm, s, a.nrows, a.order, a.b, a.a_rowptr,
+                               a.a_col, a.a_vals, a.p_rowptr, a.p_col, a.g_vals, a.nlds, scr, stride, a.counter,
+                               a.bad_row);
+            break;
+        case 128:
+            hipLaunchKernelGGL(k_fsai_setup<128>, dim3(grid), dim3(128), shm, s, a.nrows, a.order, a.b, a.a_rowptr,
+                               a.a_col, a.a_vals, a.p_rowptr, a.p_col, a.g_vals, a.nlds, scr, stride, a.counter,
+                               a.bad_row);
+            break;
+        default:
+            hipLaunchKernelGGL(k_fsai_setup<256>, dim3(grid), dim3(256), shm, s, a.nrows, a.order, a.b, a.a_rowptr,
+                               a.a_col, a.a_vals, a.p_rowptr, a.p_col, a.g_vals, a.nlds, scr, stride, a.counter,
+                               a.bad_row);
+            break;
+    }
+    CHF_LAUNCH_CHECK();
+    CHF_HIP(hipStreamSynchronize(s));  // scratch is released on return
+}
+
+static int pick_width(const SetupArgs& a, int nmax, hipStream_t s) {
+    if (const char* env = std::getenv("CHF_FSAI_WIDTH")) {
+        int w = std::atoi(env);
+        if (w == 64 || w == 128 || w == 256) return w;
+    }
+    TuneKey key{a.b, nmax};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) return it->second;
+    }
+    int best = 64;
+    if (a.nrows >= 4096) {
+        // time a sample: the first rows of the (size-sorted) order
+        SetupArgs smp = a;
+        smp.nrows = std::min<int64_t>(a.nrows, 8192);
+        double best_t = 1e30;
+        for (int w : {64, 128, 256}) {
+            launch_setup(w, smp, s);  // warm-up
+            auto t0 = std::chrono::steady_clock::now();
+            launch_setup(w, smp, s);
+            double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (dt < best_t) { best_t = dt; best = w; }
+        }
+    } else {
+        best = nmax > 64 ? 128 : 64;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+    return best;
+}
+
+static int max_lds_n(int b) {
+    int dev = 0;
+    CHF_HIP(hipGetDevice(&dev));
+    int lim = 0;
+    CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    // static LDS: index table + scalars
+    size_t avail = (size_t)std::min(lim, 64 * 1024) - (FSAI_MAXM * FSAI_MAXM * 4 + 64);
+    int n = FSAI_MAXN;
+    while (n > 0 && lds_bytes(n, b) > avail) --n;
+    return n;
+}
+
+// ----------------------------------------------------------- G^T builder --
+static void build_transpose_structure(const chf_fsai_s& G, std::vector<int64_t>& trow, std::vector<int32_t>& tcol,
+                                      std::vector<int64_t>& tsrc) {
+    int64_t nb = G.nb;
+    trow.assign(nb + 1, 0);
+    for (int64_t e = 0; e < G.nnz; ++e) trow[G.colidx[e] + 1]++;
+    for (int64_t j = 0; j < nb; ++j) trow[j + 1] += trow[j];
+    tcol.assign(G.nnz, 0);
+    tsrc.assign(G.nnz, 0);
+    std::vector<int64_t> fillp(trow.begin(), trow.end() - 1);
+    for (int64_t i = 0; i < nb; ++i)          // rows ascending -> stable, columns of G^T ascend
+        for (int64_t e = G.rowptr[i]; e < G.rowptr[i + 1]; ++e) {
+            int64_t j = G.colidx[e];
+            int64_t pos = fillp[j]++;
+            tcol[pos] = (int32_t)i;
+            tsrc[pos] = e;
+        }
+}
+
+void fsai_build_layouts(chf_fsai_s& G, hipStream_t s) {
+    G.plan_g = sell_plan(G.nb, G.b, G.rowptr, G.colidx, nullptr);
+    std::vector<int64_t> trow, tsrc;
+    std::vector<int32_t> tcol;
+    build_transpose_structure(G, trow, tcol, tsrc);
+    G.plan_gt = sell_plan(G.nb, G.b, trow, tcol, &tsrc);
+    sell_build(G.g64, G.plan_g, G.d_vals.p, false, CHF_F64, s);
+    sell_build(G.gt64, G.plan_gt, G.d_vals.p, true, CHF_F64, s);
+    if (G.store != CHF_F64) {
+        sell_build(G.g_lo, G.plan_g, G.d_vals.p, false, G.store, s);
+        sell_build(G.gt_lo, G.plan_gt, G.d_vals.p, true, G.store, s);
+    }
+}
+
+void validate_pattern(int64_t nb, const int64_t* rowptr, const int32_t* colidx) {
+    CHF_CHECK(rowptr && rowptr[0] == 0, CHF_EINVAL, "pattern rowptr[0] must be 0");
+    for (int64_t k = 0; k < nb; ++k) {
+        int64_t lo = rowptr[k], hi = rowptr[k + 1];
+        CHF_CHECK(hi > lo, CHF_EINVAL, "pattern row " + std::to_string(k) + " is empty (diagonal missing)");
+        CHF_CHECK(colidx[hi - 1] == k, CHF_EINVAL,
+                  "pattern row " + std::to_string(k) + ": diagonal missing or entry above the diagonal");
+        for (int64_t e = lo; e < hi; ++e) {
+            CHF_CHECK(colidx[e] >= 0, CHF_EINVAL, "negative pattern column");
+            CHF_CHECK(e == lo || colidx[e] > colidx[e - 1], CHF_EINVAL,
+                      "pattern row " + std::to_string(k) + ": columns not strictly ascending");
+        }
+    }
+}
+
+chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store, int64_t* bad_row,
+                            hipStream_t s) {
+    CHF_CHECK(P.nb == A->nb, CHF_EINVAL, "pattern and matrix sizes differ");
+    const int b = A->b;
+    const int64_t nb = A->nb;
+    std::unique_ptr<chf_fsai_s> G(new chf_fsai_s);
+    G->nb = nb;
+    G->b = b;
+    G->store = g_store;
+    G->rowptr = P.rowptr;
+    G->colidx = P.colidx;
+    G->nnz = P.rowptr[nb];
+    int nmax = 0;
+    for (int64_t k = 0; k < nb; ++k) {
+        int64_t m = P.rowptr[k + 1] - P.rowptr[k];
+        CHF_CHECK(m <= FSAI_MAXM && m * b <= FSAI_MAXN, CHF_EINVAL,
+                  "pattern row " + std::to_string(k) + " too large for the local solver");
+        nmax = std::max<int>(nmax, (int)(m * b));
+    }
+    // queue order: local size descending, then row index
+    std::vector<int64_t> order(nb);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+        return P.rowptr[x + 1] - P.rowptr[x] > P.rowptr[y + 1] - P.rowptr[y];
+    });
+    std::vector<int> pcol32(P.colidx.begin(), P.colidx.end());
+    DevBuf<int64_t> d_order(std::max<int64_t>(1, nb)), d_prow(nb + 1);
+    DevBuf<int> d_pcol(std::max<int64_t>(1, G->nnz)), d_flags(2);
+    d_order.upload(order.data(), nb, s);
+    d_prow.upload(P.rowptr.data(), nb + 1, s);
+    d_pcol.upload(pcol32.data(), G->nnz, s);
+    int init[2] = {0, INT32_MAX};
+    d_flags.upload(init, 2, s);
+    G->d_vals.alloc(std::max<int64_t>(1, G->nnz * b * b));
+    if (nb > 0) {
+        SetupArgs args{nb, d_order.p, b, A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, d_prow.p, d_pcol.p,
+                       G->d_vals.p, std::min(max_lds_n(b), nmax), d_flags.p, d_flags.p + 1, nmax};
+        int width = pick_width(args, nmax, s);
+        launch_setup(width, args, s);
+        int flags[2];
+        d_flags.download(flags, 2, s);
+        CHF_HIP(hipStreamSynchronize(s));
+        if (flags[1] != INT32_MAX) {
+            if (bad_row) *bad_row = flags[1];
+            fail(CHF_ENOTSPD, "local FSAI system of block row " + std::to_string(flags[1]) +
+                                  " is not positive definite");
+        }
+    }
+    fsai_build_layouts(*G, s);
+    CHF_HIP(hipStreamSynchronize(s));
+    return G.release();
+}
+
+void fsai_apply_impl(const chf_fsai_s& G, chf_dtype dt, const void* r, void* z, void* work, hipStream_t s) {
+    sell_spmv(G.g(dt), dt, r, work, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+    sell_spmv(G.gt(dt), dt, work, z, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+}
+
+// ---------------------------------------------------------------- Lanczos --
+// alpha_j = v . w, w <- w - alpha_j v - beta_{j-1} v_prev, beta_j = ||w||,
+// v_next = w / beta_j. Scalars stay on the device; the host reads them once.
+__global__ void k_lz_update(int64_t n, double* __restrict__ w, const double* __restrict__ v,
+                            const double* __restrict__ vprev, const double* __restrict__ alpha_j,
+                            const double* __restrict__ beta_prev) {
+    const double a = alpha_j[0];
+    const double bp = beta_prev ? beta_prev[0] : 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = w[i] - a * v[i] - bp * vprev[i];
+}
+
+__global__ void k_lz_scale(int64_t n, const double* __restrict__ w, double* __restrict__ vout,
+                           const double* __restrict__ nrm2, double* __restrict__ beta_j) {
+    const double bj = sqrt(nrm2[0]);
+    const double inv = bj > 0.0 ? 1.0 / bj : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) beta_j[0] = bj;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        vout[i] = w[i] * inv;
+}
+
+__global__ void k_scale_by_rsqrt(int64_t n, const double* __restrict__ x, double* __restrict__ y,
+                                 const double* __restrict__ nrm2) {
+    const double inv = 1.0 / sqrt(nrm2[0]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = x[i] * inv;
+}
+
+void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const double* v0, double safety,
+                  double* beta_out, double* theta_out, hipStream_t s) {
+    const int64_t n = A->nb * (int64_t)A->b;
+    CHF_CHECK(iters >= 1, CHF_EINVAL, "iters must be >= 1");
+    const int m = (int)std::min<int64_t>(iters, n);
+    const Sell& sa = A->sell(dt == CHF_F64 ? CHF_F64 : CHF_F32, s);
+    const Sell& sg = G.g(dt);
+    const Sell& sgt = G.gt(dt);
+    DevBuf<double> vbuf(3 * n), w(n), t1(n), scal(2 * m + 4), part(RED_BLOCKS);
+    double* va = vbuf.p;
+    double* vb = vbuf.p + n;
+    double* vc = vbuf.p + 2 * n;
+    double* alphas = scal.p;
+    double* betas = scal.p + m;
+    double* tmp = scal.p + 2 * m;
+    int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    dot(CHF_F64, v0, v0, n, tmp, part.p, s);
+    hipLaunchKernelGGL(k_scale_by_rsqrt, dim3(grid), dim3(256), 0, s, n, v0, va, (const double*)tmp);
+    CHF_LAUNCH_CHECK();
+    fill_zero(vb, n * 8, s);
+    double* v = va;
+    double* vprev = vb;
+    double* spare = vc;
+    for (int j = 0; j < m; ++j) {
+        // w = G A G^T v in FP64 arithmetic on the stored operators
+        sell_spmv(sgt, CHF_F64, v, w.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        sell_spmv(sa, CHF_F64, w.p, t1.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        sell_spmv(sg, CHF_F64, t1.p, w.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        dot(CHF_F64, v, w.p, n, alphas + j, part.p, s);
+        hipLaunchKernelGGL(k_lz_update, dim3(grid), dim3(256), 0, s, n, w.p, (const double*)v,
+                           (const double*)vprev, (const double*)(alphas + j),
+                           (const double*)(j > 0 ? betas + j - 1 : nullptr));
+        CHF_LAUNCH_CHECK();
+        if (j == m - 1) break;
+        dot(CHF_F64, w.p, w.p, n, tmp, part.p, s);
+        hipLaunchKernelGGL(k_lz_scale, dim3(grid), dim3(256), 0, s, n, (const double*)w.p, spare,
+                           (const double*)tmp, betas + j);
+        CHF_LAUNCH_CHECK();
+        double* nv = spare;
+        spare = vprev;
+        vprev = v;
+        v = nv;
+    }
+    std::vector<double> h(2 * m);
+    CHF_HIP(hipMemcpyAsync(h.data(), scal.p, 2 * m * 8, hipMemcpyDeviceToHost, s));
+    CHF_HIP(hipStreamSynchronize(s));
+    std::vector<double> al, be;
+    double amax = 0;
+    for (int j = 0; j < m; ++j) {
+        al.push_back(h[j]);
+        amax = std::max(amax, std::fabs(h[j]));
+        if (j == m - 1) break;
+        double bj = h[m + j];
+        if (!(bj >= 1e-12 * amax)) break;
+        be.push_back(bj);
+    }
+    double theta = al.size() == 1 ? al[0] : tridiag_max_eig(al, be);
+    CHF_CHECK(std::isfinite(theta) && theta > 0, CHF_EINVAL, "Lanczos produced a non-positive estimate");
+    if (theta_out) *theta_out = theta;
+    if (beta_out) *beta_out = safety * theta;
+}
+
+}  // namespace chf
+
+using namespace chf;
+
+extern "C" int chf_pattern_lower(chf_bsr A, chf_pattern* out) {
+    return guarded([&] {
+        CHF_CHECK(A && out, CHF_EINVAL, "NULL argument");
+        std::unique_ptr<chf_pattern_s> P(new chf_pattern_s);
+        P->nb = A->nb;
+        P->rowptr.assign(A->nb + 1, 0);
+        for (int64_t k = 0; k < A->nb; ++k) {
+            bool diag = false;
+            for (int64_t e = A->rowptr[k]; e < A->rowptr[k + 1]; ++e) {
+                int32_t j = A->colidx[e];
+                if (j < k) P->colidx.push_back(j);
+                if (j == k) diag = true;
+            }
+            (void)diag;
+            P->colidx.push_back((int32_t)k);
+            P->rowptr[k + 1] = (int64_t)P->colidx.size();
+        }
+        *out = P.release();
+    });
+}
+
+extern "C" int chf_pattern_from_csr(int64_t nb, const int64_t* rowptr, const int32_t* colidx, chf_pattern* out) {
+    return guarded([&] {
+        CHF_CHECK(out && nb >= 0 && rowptr && (nb == 0 || colidx), CHF_EINVAL, "bad argument");
+        validate_pattern(nb, rowptr, colidx);
+        std::unique_ptr<chf_pattern_s> P(new chf_pattern_s);
+        P->nb = nb;
+        P->rowptr.assign(rowptr, rowptr + nb + 1);
+        P->colidx.assign(colidx, colidx + rowptr[nb]);
+        *out = P.release();
+    });
+}
+
+extern "C" int chf_pattern_info(chf_pattern P, int64_t* nb, int64_t* nnz) {
+    return guarded([&] {
+        CHF_CHECK(P, CHF_EINVAL, "NULL handle");
+        if (nb) *nb = P->nb;
+        if (nnz) *nnz = P->rowptr[P->nb];
+    });
+}
+
+extern "C" int chf_pattern_export(chf_pattern P, int64_t* rowptr, int32_t* colidx) {
+    return guarded([&] {
+        CHF_CHECK(P, CHF_EINVAL, "NULL handle");
+        if (rowptr) std::memcpy(rowptr, P->rowptr.data(), (P->nb + 1) * 8);
+        if (colidx) std::memcpy(colidx, P->colidx.data(), P->colidx.size() * 4);
+    });
+}
+
+extern "C" int chf_pattern_destroy(chf_pattern P) {
+    return guarded([&] { delete P; });
+}
+
+extern "C" int chf_fsai_setup(chf_bsr A, chf_pattern P, chf_dtype g_store, chf_fsai* out, int64_t* bad_row) {
+    return guarded([&] {
+        CHF_CHECK(A && P && out, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(g_store == CHF_F64 || g_store == CHF_F32 || g_store == CHF_BF16, CHF_EINVAL, "bad dtype");
+        *out = nullptr;
+        if (bad_row) *bad_row = -1;
+        *out = fsai_setup_impl(A, *P, g_store, bad_row, 0);
+    });
+}
+
+extern "C" int chf_fsai_destroy(chf_fsai G) {
+    return guarded([&] { delete G; });
+}
+
+extern "C" int chf_fsai_export(chf_fsai G, double* vals) {
+    return guarded([&] {
+        CHF_CHECK(G && vals, CHF_EINVAL, "NULL argument");
+        G->d_vals.download(vals, (size_t)G->nnz * G->b * G->b, 0);
+        CHF_HIP(hipStreamSynchronize(0));
+    });
+}
+
+extern "C" int chf_fsai_apply(chf_fsai G, chf_dtype dtype, const void* r, void* z, void* work,
+                              hipStream_t stream) {
+    return guarded([&] {
+        CHF_CHECK(G && r && z && work, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(dtype == CHF_F64 || G->store == dtype || (dtype == CHF_F32 && G->store == CHF_BF16),
+                  CHF_EINVAL, "dtype does not match the factor's storage");
+        chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
+        chf_dtype use = dtype == CHF_F64 ? CHF_F64 : G->store;
+        sell_spmv(G->g(use), vec, r, work, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
+        sell_spmv(G->gt(use), vec, work, z, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
+    });
+}
+
+extern "C" int chf_lmax_lanczos(chf_bsr A, chf_fsai G, chf_dtype dtype, int iters, const double* v0,
+                                double safety, double* beta, double* theta, hipStream_t stream) {
+    return guarded([&] {
+        CHF_CHECK(A && G && v0, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(A->nb == G->nb && A->b == G->b, CHF_EINVAL, "A and G sizes differ");
+        CHF_CHECK(dtype == CHF_F64 || dtype == G->store, CHF_EINVAL, "dtype does not match the factor's storage");
+        lanczos_impl(A, *G, dtype, iters, v0, safety, beta, theta, stream);
+    });
+}

@@ -13,9 +13,11 @@ from .generator import (  # noqa: F401
     make_problem,
     prolongator_1d,
     prolongator,
+    level_basis,
     rhs,
     lanczos_starts,
     uniform_start,
     grid_sizes,
+    mlp_init,
 )
 from .configs import CONFIGS, ProblemConfig  # noqa: F401

@@ -98,6 +98,7 @@ class Problem:
     vals: np.ndarray       # float64, (nnzb, b, b), each block row-major
     dstencil: sp.csr_matrix = field(repr=False)  # the scalar D
     rfac: np.ndarray = field(repr=False)         # (nb, b, b) block-diagonal R
+    rinv: np.ndarray = field(repr=False)         # (nb, b, b) R^{-1} = diag(exp(-u)) Q^T
 
     @property
     def nb(self) -> int:
@@ -130,8 +131,10 @@ def make_problem(n: int, dim: int, b: int, power: int, seed: int = 0,
         q = _haar_orthogonal(streams[STREAM_Q], nb, b)
         u = streams[STREAM_U].uniform(-1.0, 1.0, size=(nb, b))
         rfac = q * np.exp(u)[:, None, :]          # Q_i diag(exp u_i)
+        rinv = np.swapaxes(q, 1, 2) * np.exp(-u)[:, :, None]
     else:
         rfac = np.broadcast_to(np.eye(b), (nb, b, b)).copy()
+        rinv = rfac.copy()
     rowptr = dmat.indptr.astype(np.int64)
     colidx = dmat.indices.astype(np.int32)
     rows = np.repeat(np.arange(nb, dtype=np.int64), np.diff(rowptr))
@@ -145,7 +148,7 @@ def make_problem(n: int, dim: int, b: int, power: int, seed: int = 0,
         np.matmul(np.swapaxes(ri, 1, 2), rj, out=vals[s:e])
         vals[s:e] *= dval[s:e, None, None]
     return Problem(n=n, dim=dim, b=b, power=power, seed=seed, rowptr=rowptr,
-                   colidx=colidx, vals=vals, dstencil=dmat, rfac=rfac)
+                   colidx=colidx, vals=vals, dstencil=dmat, rfac=rfac, rinv=rinv)
 
 
 def pum_block_size(p: int, dim: int) -> int:
@@ -187,6 +190,18 @@ def prolongator(nc: int, dim: int) -> sp.csr_matrix:
     return p
 
 
+def level_basis(p: Problem, levels: int) -> list:
+    """Block-diagonal basis change of each level's prolongation.
+
+    The patch prolongator P_s (x) I_b interpolates the coefficients of the
+    unrotated local bases; the finest level's local bases are rotated by R
+    (A = R^T (D (x) I_b) R), so its prolongation is R^{-1} (P_s (x) I_b). The
+    Galerkin coarse operators carry no rotation (identity, None). Entry l
+    belongs to the prolongation from level l+1 to level l.
+    """
+    return [p.rinv if l == 0 else None for l in range(levels - 1)]
+
+
 def rhs(seed: int, ndof: int) -> np.ndarray:
     """Right-hand side ~ N(0, 1)^ndof from the seed's RHS stream."""
     return _streams(seed)[STREAM_RHS].standard_normal(ndof)
@@ -202,3 +217,13 @@ def lanczos_starts(seed: int, sizes: list[int]) -> list[np.ndarray]:
 def uniform_start(seed: int, ndof: int) -> np.ndarray:
     """Initial error with entries in U(-1, 1) for convergence-factor runs."""
     return np.random.default_rng(np.random.SeedSequence([seed, 7919])).uniform(-1.0, 1.0, ndof)
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """He-uniform initial weights (zero biases) for the 4-64-64-1 network,
+    in the layout W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4545]))
+    w1 = rng.uniform(-1, 1, (64, 4)) * np.sqrt(6.0 / 4)
+    w2 = rng.uniform(-1, 1, (64, 64)) * np.sqrt(6.0 / 64)
+    w3 = rng.uniform(-1, 1, 64) * np.sqrt(6.0 / 64)
+    return np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, [0.0]]).astype(np.float32)

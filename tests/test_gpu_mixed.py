@@ -1,0 +1,101 @@
+"""Mixed precision (A and G stored in FP32, G optionally BF16, FP32 vectors
+and accumulation inside the V-cycle, FP64 outer PCG): per-application error
+against the FP64 oracle and convergence of the outer PCG. Parity of the mixed
+form is unpinned beyond the storage rounding; the bounds below follow from
+the unit roundoffs (FP32 6e-8, BF16 3.9e-3) times the smoother's modest
+amplification."""
+import numpy as np
+import pytest
+
+from oracle import chebyshev, fsai, lanczos, multilevel, solver
+from oracle.bsr import Bsr, from_problem
+from oracle.mixed import round_bf16, round_f32
+from problems import lanczos_starts, make_problem, rhs
+from tests.helpers import dev, gpu_levels, hierarchy_inputs, host, rel_err, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def chf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2509_06744_amd as m
+    m.lib()
+    return m
+
+
+@pytest.mark.parametrize("store,tol_fp64,tol_rounded", [(1, 2e-5, 2e-5), (2, 5e-2, 2e-5)])
+def test_mixed_smoother_error(chf, store, tol_fp64, tol_rounded):
+    import torch
+    p = make_problem(32, 2, 10, 2, seed=0)
+    a = from_problem(p)
+    prow, pcol = fsai.pattern_lower(a)
+    og = fsai.fsai(a, prow, pcol)
+    asp, gsp = a.scipy(), og.scipy()
+    gtsp = gsp.T.tocsr()
+    beta, _ = lanczos.lmax(lambda v: gsp @ (asp @ (gtsp @ v)), lanczos_starts(0, [p.ndof])[0])
+    b_ = rhs(0, p.ndof)
+    want = chebyshev.cheb4(lambda v: asp @ v, lambda v: gtsp @ (gsp @ v), b_, None, beta, 4, x_is_zero=True)
+    # the same algorithm on the rounded operators, evaluated in FP64
+    ar = Bsr(a.rowptr, a.colidx, round_f32(a.vals), 10).scipy()
+    rg = round_bf16 if store == 2 else round_f32
+    gr = Bsr(og.rowptr, og.colidx, rg(og.vals), 10).scipy()
+    grt = gr.T.tocsr()
+    want_r = chebyshev.cheb4(lambda v: ar @ v, lambda v: grt @ (gr @ v), b_, None, beta, 4, x_is_zero=True)
+    A = upload(p)
+    G = chf.fsai_setup(A, chf.pattern_lower(A), g_store=store)
+    x = torch.zeros(p.ndof, dtype=torch.float32, device="cuda")
+    work = torch.zeros(3 * p.ndof, dtype=torch.float32, device="cuda")
+    chf.cheb4_smooth(A, G, beta, 4, dev(b_, torch.float32), x, x_is_zero=True, work=work, dtype=store)
+    e64 = rel_err(host(x), want)
+    er = rel_err(host(x), want_r)
+    print(f"store={store}: error vs FP64 oracle {e64:.3e}, vs rounded-operator oracle {er:.3e}")
+    assert e64 < tol_fp64 and er < tol_rounded
+
+
+@pytest.mark.parametrize("store", [1, 2])
+def test_mixed_lanczos_on_rounded_operators(chf, store):
+    p = make_problem(16, 2, 10, 2, seed=0)
+    a = from_problem(p)
+    prow, pcol = fsai.pattern_lower(a)
+    og = fsai.fsai(a, prow, pcol)
+    rg = round_bf16 if store == 2 else round_f32
+    ar = Bsr(a.rowptr, a.colidx, round_f32(a.vals), 10).scipy()
+    gr = Bsr(og.rowptr, og.colidx, rg(og.vals), 10).scipy()
+    grt = gr.T.tocsr()
+    v0 = lanczos_starts(0, [p.ndof])[0]
+    want, wt = lanczos.lmax(lambda v: gr @ (ar @ (grt @ v)), v0)
+    A = upload(p)
+    G = chf.fsai_setup(A, chf.pattern_lower(A), g_store=store)
+    beta, theta = chf.lmax_lanczos(A, G, dev(v0), dtype=store)
+    assert abs(theta - wt) < 1e-8 * wt
+
+
+@pytest.mark.parametrize("store", [1, 2])
+def test_mixed_pcg_converges(chf, store):
+    import torch
+    p = make_problem(32, 2, 10, 2, seed=0)
+    b_ = rhs(0, p.ndof)
+    A64, L64, _, _ = gpu_levels(p, 3, 3, 0)
+    x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    it64, _, _, _ = chf.pcg_solve(L64, dev(b_), x, rtol=1e-8, maxit=100)
+    A, L, _, _ = gpu_levels(p, 3, 3, 0, dtype=store)
+    x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    it, hist, tr, _ = chf.pcg_solve(L, dev(b_), x, rtol=1e-8, maxit=100, flexible=True)
+    print(f"store={store}: PCG iterations FP64 {it64}, mixed {it}, true relres {tr:.2e}")
+    assert hist[-1] <= 1e-8 and tr < 1e-7
+    assert it <= it64 + (2 if store == 1 else 8)
+
+
+def test_mixed_triharmonic_to_1e10(chf):
+    """b = 21 triharmonic-like (D = L^3), adaptive t_max 8, mixed FP32, outer
+    FP64 PCG to a recursive relative residual of 1e-10."""
+    import torch
+    p = make_problem(32, 2, 21, 3, seed=0)
+    b_ = rhs(0, p.ndof)
+    A, L, _, _ = gpu_levels(p, 2, 4, 1, tmax=8, dtype=1)
+    x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    it, hist, tr, _ = chf.pcg_solve(L, dev(b_), x, rtol=1e-10, maxit=300, flexible=True)
+    print(f"triharmonic mixed: {it} iterations, true relres {tr:.2e}")
+    assert hist[-1] <= 1e-10

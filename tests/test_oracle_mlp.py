@@ -1,0 +1,62 @@
+"""Pins for the MLP oracle: backprop against central finite differences and
+closed-form features on the unrotated problem D (x) I_b."""
+import math
+
+import numpy as np
+
+from oracle import mlp
+from oracle.bsr import from_problem
+from problems import make_problem, mlp_init
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    p = mlp_init(3).astype(np.float64)
+    p[256:320] = 0.1 * rng.standard_normal(64)     # nonzero biases
+    p[4416:4480] = 0.1 * rng.standard_normal(64)
+    x = rng.standard_normal((40, 4))
+    y = (rng.uniform(size=40) < 0.4).astype(np.float64)
+    lval, g = mlp.loss_grad(p, x, y)
+    assert abs(lval - mlp.loss(p, x, y)) < 1e-14
+    idx = rng.choice(mlp.NPARAM, 200, replace=False)
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(mlp.NPARAM)
+        e[i] = h
+        fd = (mlp.loss(p + e, x, y) - mlp.loss(p - e, x, y)) / (2 * h)
+        assert abs(fd - g[i]) < 1e-7 + 1e-5 * abs(g[i]), i
+
+
+def test_loss_closed_form_zero_net():
+    p = np.zeros(mlp.NPARAM)
+    x = np.ones((5, 4))
+    y = np.array([0, 1, 1, 0, 1.0])
+    assert abs(mlp.loss(p, x, y) - math.log(2)) < 1e-15
+
+
+def test_features_closed_form_unrotated():
+    # with R = I: A_ij = D_ij I_b, so f0 = |D_kc| / sqrt(D_kk D_cc),
+    # f1 = |D_ck / D_cc| sqrt(b), f3 = -b log(1 - D_kc^2 / (D_kk D_cc))
+    n, b = 6, 3
+    p = make_problem(n, 2, b, 2, seed=0, rotate=False)
+    a = from_problem(p)
+    d = p.dstencil.toarray()
+    crow, ccol, feats = mlp.features(a, n, n, rows=[14, 21, 35])
+    for k, (cand, f) in feats.items():
+        for c, fc in zip(cand, f):
+            dkc, dkk, dcc = d[k, c], d[k, k], d[c, c]
+            assert abs(fc[0] - abs(dkc) / math.sqrt(dkk * dcc)) < 1e-12
+            assert abs(fc[1] - abs(dkc / dcc) * math.sqrt(b)) < 1e-12
+            assert abs(fc[2] - math.hypot(c % n - k % n, c // n - k // n)) < 1e-12
+            want = -b * math.log1p(-dkc * dkc / (dkk * dcc))
+            assert abs(fc[3] - want) < 1e-12 * max(1.0, want)
+
+
+def test_topk_ties_to_smaller_column():
+    crow = np.array([0, 0, 1, 3])
+    ccol = np.array([0, 1, 0])
+    score = np.array([0.5, 2.0, 2.0])
+    prow, pcol = mlp.topk_pattern(crow, ccol, score, 1)
+    assert list(pcol[prow[2]:prow[3]]) == [0, 2]
+    assert list(pcol[prow[1]:prow[2]]) == [0, 1]
+    assert list(pcol[prow[0]:prow[1]]) == [0]

@@ -118,3 +118,28 @@ def test_pcg_flexible_variant_close():
     r2 = multilevel.pcg(levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, 3), b, 1e-8, 100,
                         flexible=True)
     assert abs(r1[1] - r2[1]) <= 1
+
+
+def test_basis_transfer_reduces_to_scalar_galerkin():
+    # With P = R^{-1} (P_s (x) I_b), T^T A T = D (x) I_b, so the coarse operator
+    # is the scalar Galerkin product of D repeated per block component.
+    import scipy.sparse as sp
+    from problems import level_basis
+    p = make_problem(16, 2, 3, 2, seed=5)
+    a = from_problem(p)
+    ps = prolongator(8, 2)
+    ac = multilevel.galerkin(a, ps, level_basis(p, 2)[0]).dense()
+    dc = (ps.T @ p.dstencil @ ps).toarray()
+    want = np.kron(dc, np.eye(3))
+    assert abs(ac - want).max() < 1e-12 * abs(want).max()
+
+
+def test_basis_transfer_pcg_iterations_bounded():
+    from tests.helpers import oracle_levels
+    its = []
+    for n in (16, 32):
+        p = make_problem(n, 2, 10, 2, seed=0)
+        lv = oracle_levels(p, 3)
+        _, it, _, _ = multilevel.pcg(lv[0].apply_a, lambda r: multilevel.vcycle(lv, 0, r, 3), rhs(0, p.ndof), 1e-8, 200)
+        its.append(it)
+    assert its[1] <= 15 and its[1] <= its[0] + 6
