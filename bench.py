@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-grid", type=int, default=32, help="patches per side of the oracle's timing sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run 3 plain device copies of 1 GiB (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -102,6 +104,13 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n, b, L, k = args.n, 10, args.levels, args.degree
     log(f"generating {n}x{n} b={b} problem")
     t0 = time.perf_counter()

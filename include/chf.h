@@ -149,6 +149,9 @@ int chf_levels_add_coarse(chf_levels L, int64_t nc, const int64_t* p_rowptr,
  * (the coarsest level reports -2). */
 int chf_levels_setup(chf_levels L, const chf_level_opts* opts, const double* const* v0,
                      int64_t* bad_row);
+/* Use pattern P (copied; lower triangular with the diagonal) on level `level`
+ * instead of opts->pattern, e.g. a learned proposal. Before chf_levels_setup. */
+int chf_levels_set_pattern(chf_levels L, int level, chf_pattern P);
 int chf_levels_destroy(chf_levels L);
 int chf_levels_info(chf_levels L, int* nlevels, int64_t* nb_per_level /* [nlevels] or NULL */);
 /* Borrowed handles of level l (valid while L lives; G is NULL on the coarsest). */
@@ -169,6 +172,9 @@ int chf_pcg_solve(chf_levels L, const double* b, double* x, double rtol, int max
                   hipStream_t stream);
 
 /* ------------------------------------------------------- learned pattern -- */
+/* Not part of the paper: a small network, trained on patterns that Algorithm 1
+ * produces, proposes the factor pattern; Algorithm 1 stays the fallback and
+ * the reference it is judged against. */
 /* Candidate features for the learned pattern proposer: for each block row k
  * and each candidate c in the strictly lower part of the row pattern of A^2,
  * 4 FP32 features: ||A_kc||_F, ||A_cc^{-1} A_ck||_F, patch distance |k - c|
@@ -193,6 +199,15 @@ int chf_mlp_loss_grad(chf_mlp net, const float* feats, const float* labels, int6
 int chf_mlp_train_step(chf_mlp net, const float* feats, const float* labels, int64_t n,
                        float lr, float beta1, float beta2, float eps, float* loss_host,
                        hipStream_t stream);
+/* Labels for the candidates of chf_mlp_candidates (device float[ncand]):
+ * 1 where the candidate belongs to P (e.g. the pattern of Algorithm 1). */
+int chf_mlp_labels(chf_bsr A, chf_pattern P, float* labels, hipStream_t stream);
+/* `epochs` passes of mini-batch Adam over n rows in the order given by the
+ * device permutation perm (int64[n], NULL = identity), `batch` rows per step.
+ * loss_hist (host float[epochs], may be NULL) receives each epoch's mean loss. */
+int chf_mlp_train(chf_mlp net, const float* feats, const float* labels, int64_t n, const int64_t* perm,
+                  int64_t batch, int epochs, float lr, float beta1, float beta2, float eps,
+                  float* loss_hist, hipStream_t stream);
 /* Pattern from the t highest-scoring candidates per row (ties to the smaller
  * column), diagonal added. */
 int chf_mlp_propose(chf_bsr A, chf_mlp net, int32_t nx, int32_t ny, int t, chf_pattern* out);

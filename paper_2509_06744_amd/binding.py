@@ -13,9 +13,9 @@ __all__ = [
     "pattern_lower", "pattern_from_csr", "pattern_adaptive", "pattern_export",
     "fsai_setup", "fsai_export", "fsai_apply", "lmax_lanczos", "cheb4_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
-    "levels_set_beta", "levels_info", "vcycle", "pcg_solve",
+    "levels_set_beta", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
     "mlp_candidates", "mlp_features", "mlp_create", "mlp_get_params", "mlp_forward",
-    "mlp_loss_grad", "mlp_train_step", "mlp_propose",
+    "mlp_loss_grad", "mlp_train_step", "mlp_propose", "mlp_labels", "mlp_train",
     "EXPORTED",
 ]
 
@@ -60,6 +60,7 @@ EXPORTED = {
     "chf_levels_add_coarse": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "chf_levels_setup": (C.c_int, [_vp, C.POINTER(LevelOpts), C.POINTER(_vp), _pi64]),
     "chf_levels_destroy": (C.c_int, [_vp]),
+    "chf_levels_set_pattern": (C.c_int, [_vp, C.c_int, _vp]),
     "chf_levels_info": (C.c_int, [_vp, _pint, _vp]),
     "chf_levels_get": (C.c_int, [_vp, C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]),
     "chf_levels_get_beta": (C.c_int, [_vp, C.c_int, _pd]),
@@ -75,6 +76,8 @@ EXPORTED = {
     "chf_mlp_loss_grad": (C.c_int, [_vp, _vp, _vp, _i64, _pf, _vp, _vp]),
     "chf_mlp_train_step": (C.c_int, [_vp, _vp, _vp, _i64, _flt, _flt, _flt, _flt, _pf, _vp]),
     "chf_mlp_propose": (C.c_int, [_vp, _vp, _i32, _i32, C.c_int, C.POINTER(_vp)]),
+    "chf_mlp_labels": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "chf_mlp_train": (C.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, C.c_int, _flt, _flt, _flt, _flt, _vp, _vp]),
 }
 
 _LIB = None
@@ -314,6 +317,10 @@ def levels_setup(L: Levels, degree=4, pattern=0, tmax=0, tau=1.0, lanczos_iters=
         raise err
 
 
+def levels_set_pattern(L: Levels, level: int, P: Pattern):
+    _check(_fn("chf_levels_set_pattern")(L.h, int(level), P.h))
+
+
 def levels_info(L: Levels):
     nl = C.c_int()
     _check(_fn("chf_levels_info")(L.h, C.byref(nl), None))
@@ -406,3 +413,17 @@ def mlp_propose(A: Bsr, net: Mlp, nx: int, ny: int, t: int) -> Pattern:
     out = C.c_void_p()
     _check(_fn("chf_mlp_propose")(A.h, net.h, int(nx), int(ny), int(t), C.byref(out)))
     return Pattern(out)
+
+
+def mlp_labels(A: Bsr, P: Pattern, labels, stream=None):
+    _check(_fn("chf_mlp_labels")(A.h, P.h, _ptr(labels), _stream(stream)))
+
+
+def mlp_train(net: Mlp, feats, labels, n: int, perm=None, batch=8192, epochs=1, lr=1e-3, beta1=0.9, beta2=0.999,
+              eps=1e-8, stream=None):
+    """Returns the mean loss of each epoch."""
+    hist = np.zeros(max(epochs, 1), np.float32)
+    _check(_fn("chf_mlp_train")(net.h, _ptr(feats), _ptr(labels), int(n), _ptr(perm), int(batch), int(epochs),
+                                float(lr), float(beta1), float(beta2), float(eps), hist.ctypes.data_as(C.c_void_p),
+                                _stream(stream)))
+    return hist[:epochs]

@@ -51,15 +51,18 @@ SellPlan sell_plan(int64_t nb, int b, const std::vector<int64_t>& rowptr,
 }
 
 template <typename T>
-__global__ void k_sell_pack(int64_t total, int b, int S, int L, const int64_t* __restrict__ src,
+__global__ void k_sell_pack(int64_t total, int b, int S, int L, int V, const int64_t* __restrict__ src,
                             const double* __restrict__ blocks, int transpose, T* __restrict__ out) {
     const int64_t bl = (int64_t)b * L;
+    const int LV = L * V;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t slot = e / bl;
-        int64_t rem = e - slot * bl;
-        int c = (int)(rem / L);
-        int lane = (int)(rem - (int64_t)c * L);
+        int rem = (int)(e - slot * bl);
+        int q = rem / LV;
+        int rem2 = rem - q * LV;
+        int lane = rem2 / V;
+        int c = q * V + (rem2 - lane * V);
         int lr = lane / b, r = lane - lr * b;
         int64_t sb = src[slot * S + lr];
         double v = 0.0;
@@ -71,12 +74,17 @@ __global__ void k_sell_pack(int64_t total, int b, int S, int L, const int64_t* _
     }
 }
 
+// Lane vector width of the layout: pairs of columns for the block sizes with
+// a specialised SpMV (16-byte FP64 loads for b = 10).
+static int sell_vec_width(int b) { return b == 10 ? 2 : 1; }
+
 void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, bool transpose,
                 chf_dtype dtype, hipStream_t s) {
     out.nb = plan.nb;
     out.b = plan.b;
     out.S = plan.S;
     out.L = plan.L;
+    out.V = sell_vec_width(plan.b);
     out.nslices = plan.nslices;
     out.nslots = plan.nslots;
     out.dtype = dtype;
@@ -92,13 +100,13 @@ void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, boo
         int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
         if (dtype == CHF_F64)
             hipLaunchKernelGGL((k_sell_pack<double>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
-                               src.p, d_src_blocks, (int)transpose, (double*)out.vals.p);
+                               out.V, src.p, d_src_blocks, (int)transpose, (double*)out.vals.p);
         else if (dtype == CHF_F32)
             hipLaunchKernelGGL((k_sell_pack<float>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
-                               src.p, d_src_blocks, (int)transpose, (float*)out.vals.p);
+                               out.V, src.p, d_src_blocks, (int)transpose, (float*)out.vals.p);
         else
             hipLaunchKernelGGL((k_sell_pack<bf16_t>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
-                               src.p, d_src_blocks, (int)transpose, (bf16_t*)out.vals.p);
+                               out.V, src.p, d_src_blocks, (int)transpose, (bf16_t*)out.vals.p);
         CHF_LAUNCH_CHECK();
     }
     // src is freed at scope exit; make sure the pack has consumed it.
@@ -108,9 +116,56 @@ void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, boo
 // ------------------------------------------------------------------ SpMV --
 // One 64-wide wavefront per slice; lane = local_row * b + r owns output
 // scalar r of block row slice*S + local_row and accumulates
-// sum_j sum_c block_j[r][c] * x[col_j * b + c] in TV precision. Each
-// matrix load instruction reads L contiguous elements.
-template <int BT, typename TA, typename TV, int EPI>
+// sum_j sum_c block_j[r][c] * x[col_j * b + c] in TV precision. Each matrix
+// load instruction reads L * V contiguous elements; x is gathered V values at
+// a time. Workgroups are mapped so that each of the 8 XCDs (which receive
+// workgroups round-robin) works on one contiguous range of slices, keeping the
+// x gathers of neighbouring block rows in that XCD's L2.
+template <int V, typename TA, typename TV>
+struct Pair;
+template <typename TA, typename TV>
+struct Pair<1, TA, TV> {
+    __device__ static inline TV dot(const TA* v, const TV* x) { return load_as<TV>(v) * x[0]; }
+};
+template <typename TV>
+struct Pair<2, double, TV> {
+    __device__ static inline TV dot(const double* v, const TV* x) {
+        const double2 a = *reinterpret_cast<const double2*>(v);
+        if constexpr (sizeof(TV) == 8) {
+            const double2 y = *reinterpret_cast<const double2*>(x);
+            return a.x * y.x + a.y * y.y;
+        } else {
+            return (TV)a.x * x[0] + (TV)a.y * x[1];
+        }
+    }
+};
+template <typename TV>
+struct Pair<2, float, TV> {
+    __device__ static inline TV dot(const float* v, const TV* x) {
+        const float2 a = *reinterpret_cast<const float2*>(v);
+        if constexpr (sizeof(TV) == 4) {
+            const float2 y = *reinterpret_cast<const float2*>(x);
+            return a.x * y.x + a.y * y.y;
+        } else {
+            return (TV)a.x * x[0] + (TV)a.y * x[1];
+        }
+    }
+};
+template <typename TV>
+struct Pair<2, bf16_t, TV> {
+    __device__ static inline TV dot(const bf16_t* v, const TV* x) {
+        const uint32_t u = *reinterpret_cast<const uint32_t*>(v);
+        return (TV)bf16_bits_to_f32((uint16_t)(u & 0xffffu)) * x[0] + (TV)bf16_bits_to_f32((uint16_t)(u >> 16)) * x[1];
+    }
+};
+
+__device__ inline int64_t xcd_slice_block(int64_t nwork_blocks) {
+    // gridDim.x is a multiple of 8; block id b runs on XCD b % 8
+    const int64_t per = gridDim.x / 8;
+    return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <int BT, int V, typename TA, typename TV, int EPI>
 __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, int brt,
                                                    const int* __restrict__ soff, const int* __restrict__ cols,
                                                    const TA* __restrict__ vals, const TV* __restrict__ x,
@@ -119,7 +174,7 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, 
     const int b = BT ? BT : brt;
     const int S = 64 / b;
     const int L = S * b;
-    const int64_t slice = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t slice = xcd_slice_block((nslices + 3) / 4) * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (slice >= nslices || lane >= L) return;
     const int lr = lane / b;
@@ -128,14 +183,24 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, 
     if (row >= nb) return;
     const int j0 = soff[slice], j1 = soff[slice + 1];
     TV acc = 0;
-    for (int j = j0; j < j1; ++j) {
-        const int col = cols[(int64_t)j * S + lr];
-        const TA* v = vals + (int64_t)j * b * L + lane;
-        const TV* xc = x + (int64_t)col * b;
-        if constexpr (BT > 0) {
+    if constexpr (BT > 0) {
+        constexpr int NQ = BT / V;
+        const int64_t stride = (int64_t)NQ * L * V;
+        const TA* v = vals + (int64_t)j0 * stride + lane * V;
+        const int* cp = cols + (int64_t)j0 * S + lr;
+#pragma unroll 2
+        for (int j = j0; j < j1; ++j) {
+            const TV* xc = x + (int64_t)(*cp) * BT;
 #pragma unroll
-            for (int c = 0; c < BT; ++c) acc += load_as<TV>(v + c * L) * xc[c];
-        } else {
+            for (int q = 0; q < NQ; ++q) acc += Pair<V, TA, TV>::dot(v + q * L * V, xc + q * V);
+            v += stride;
+            cp += S;
+        }
+    } else {
+        for (int j = j0; j < j1; ++j) {
+            const int col = cols[(int64_t)j * S + lr];
+            const TA* v = vals + (int64_t)j * b * L + lane;
+            const TV* xc = x + (int64_t)col * b;
             for (int c = 0; c < b; ++c) acc += load_as<TV>(v + c * L) * xc[c];
         }
     }
@@ -157,22 +222,23 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, 
     }
 }
 
-template <int BT, typename TA, typename TV>
+template <int BT, int V, typename TA, typename TV>
 static void launch_spmv_t(const Sell& A, const void* x, void* y, const void* bv, int epi, void* p, void* xo,
                           double alpha, double beta, hipStream_t s) {
-    dim3 grid((unsigned)((A.nslices + 3) / 4)), block(256);
-    if (grid.x == 0) return;
+    const int64_t nblk = (A.nslices + 3) / 4;
+    if (nblk == 0) return;
+    dim3 grid((unsigned)((nblk + 7) / 8 * 8)), block(256);
     auto args = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, block, 0, s, A.nslices, A.nb, A.b, A.slice_off.p, A.cols.p,
                            (const TA*)A.vals.p, (const TV*)x, (TV*)y, (const TV*)bv, (TV*)p, (TV*)xo, (TV)alpha,
                            (TV)beta);
     };
     switch (epi) {
-        case EPI_AX: args(k_sell_spmv<BT, TA, TV, EPI_AX>); break;
-        case EPI_RES: args(k_sell_spmv<BT, TA, TV, EPI_RES>); break;
-        case EPI_CHEB_FIRST0: args(k_sell_spmv<BT, TA, TV, EPI_CHEB_FIRST0>); break;
-        case EPI_CHEB_FIRST: args(k_sell_spmv<BT, TA, TV, EPI_CHEB_FIRST>); break;
-        default: args(k_sell_spmv<BT, TA, TV, EPI_CHEB>); break;
+        case EPI_AX: args(k_sell_spmv<BT, V, TA, TV, EPI_AX>); break;
+        case EPI_RES: args(k_sell_spmv<BT, V, TA, TV, EPI_RES>); break;
+        case EPI_CHEB_FIRST0: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST0>); break;
+        case EPI_CHEB_FIRST: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST>); break;
+        default: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB>); break;
     }
     CHF_LAUNCH_CHECK();
 }
@@ -180,10 +246,11 @@ static void launch_spmv_t(const Sell& A, const void* x, void* y, const void* bv,
 template <typename TA, typename TV>
 static void launch_spmv_b(const Sell& A, const void* x, void* y, const void* bv, int epi, void* p, void* xo,
                           double alpha, double beta, hipStream_t s) {
+    CHF_CHECK(A.V == sell_vec_width(A.b), CHF_EDEVICE, "SpMV layout width mismatch");
     switch (A.b) {
-        case 10: launch_spmv_t<10, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
-        case 21: launch_spmv_t<21, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
-        default: launch_spmv_t<0, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+        case 10: launch_spmv_t<10, 2, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+        case 21: launch_spmv_t<21, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+        default: launch_spmv_t<0, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
     }
 }
 

@@ -96,14 +96,17 @@ size_t vec_size(chf_dtype t);        // vector element size (double or float)
 // Slice-interleaved block-ELL: a slice holds S = 64 / b consecutive block
 // rows, so one 64-wide wavefront owns L = S * b output scalars (lane =
 // local_row * b + r). Slot j of slice s stores, for every lane, the b entries
-// of row r of that lane's j-th block as b consecutive runs of L values:
-//   vals[(slot_base + j) * b * L + c * L + lane] = block(row, j)[r][c].
-// One load instruction therefore reads L contiguous values. Column indices
-// are cols[(slot_base + j) * S + local_row]; padding slots point at the row's
-// own block with zero values.
+// of row r of that lane's j-th block in b / V runs of L groups of V
+// consecutive columns:
+//   vals[(((slot_base + j) * (b / V) + q) * L + lane) * V + v]
+//       = block(row, j)[r][q * V + v].
+// One load instruction therefore reads L * V contiguous values (16 bytes per
+// lane for FP64 with V = 2). Column indices are cols[(slot_base + j) * S +
+// local_row]; padding slots point at the row's own block with zero values.
 struct Sell {
     int64_t nb = 0;
     int b = 0, S = 0, L = 0;
+    int V = 1;                // consecutive columns c per lane load (see sell_build)
     int64_t nslices = 0, nslots = 0;
     chf_dtype dtype = CHF_F64;
     DevBuf<int> slice_off;    // nslices + 1 (slots)

@@ -17,6 +17,7 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
 void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const double* v0, double safety,
                   double* beta_out, double* theta_out, hipStream_t s);
 chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_t s);
+void validate_pattern(int64_t nb, const int64_t* rowptr, const int32_t* colidx);
 
 // ------------------------------------------------------------- Galerkin --
 // A_c[I, J] = sum_{i in P^T(I)} sum_{j in A(i)} sum_{J in P(j)} P_iI A_ij P_jJ.
@@ -337,6 +338,8 @@ struct chf_level_s {
     chf_bsr A = nullptr;
     bool own_A = false;
     chf_pattern P = nullptr;
+    bool preset = false;                // P given by the caller
+
     chf_fsai G = nullptr;
     double beta = 0.0;
     // prolongation from the next coarser level (host + device CSR)
@@ -650,7 +653,9 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
         const int nl = (int)H->lev.size();
         for (int l = 0; l < nl - 1; ++l) {
             chf_level_s& L = H->lev[l];
-            if (opts->pattern == 1) {
+            if (L.preset) {
+                // caller-supplied pattern (e.g. a learned proposal)
+            } else if (opts->pattern == 1) {
                 L.P = adaptive_pattern_impl(L.A, opts->tmax, opts->tau, s);
             } else {
                 chf_pattern P = nullptr;
@@ -677,6 +682,19 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
         alloc_vectors(*H);
         H->ready = true;
         CHF_HIP(hipStreamSynchronize(s));
+    });
+}
+
+extern "C" int chf_levels_set_pattern(chf_levels H, int level, chf_pattern P) {
+    return guarded([&] {
+        CHF_CHECK(H && P && level >= 0 && level + 1 < (int)H->lev.size(), CHF_EINVAL, "bad level or pattern");
+        CHF_CHECK(!H->ready, CHF_EINVAL, "hierarchy already set up");
+        chf_level_s& L = H->lev[level];
+        CHF_CHECK(P->nb == L.A->nb, CHF_EINVAL, "pattern and level sizes differ");
+        validate_pattern(P->nb, P->rowptr.data(), P->colidx.data());
+        if (L.P) delete L.P;
+        L.P = new chf_pattern_s(*P);
+        L.preset = true;
     });
 }
 

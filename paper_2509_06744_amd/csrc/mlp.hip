@@ -26,12 +26,13 @@ void mlp_features_impl(chf_bsr A, int nx, int ny, const std::vector<int64_t>& cr
 
 // Forward pass of one tile: X -> H1 -> H2 (in LDS), returns nothing; logits
 // per sample are left in `o`.
-__device__ void mlp_tile_forward(const float* P, const float* __restrict__ X, int64_t s0, int64_t n, float* Xs,
-                                 float* H1, float* H2, float* o) {
+__device__ void mlp_tile_forward(const float* P, const float* __restrict__ X, const int64_t* __restrict__ perm,
+                                 int64_t off, int64_t s0, int64_t n, float* Xs, float* H1, float* H2, float* o) {
     const int t = threadIdx.x;
     for (int e = t; e < TILE * NIN; e += MLP_NT) {
         int64_t s = s0 + e / NIN;
-        Xs[e] = s < n ? X[s * NIN + e % NIN] : 0.0f;
+        int64_t src = perm ? perm[off + s] : off + s;
+        Xs[e] = s < n ? X[src * NIN + e % NIN] : 0.0f;
     }
     __syncthreads();
     for (int e = t; e < TILE * H; e += MLP_NT) {
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(MLP_NT) void k_mlp_forward(const float* __restrict_
     for (int e = threadIdx.x; e < NPARAM; e += MLP_NT) P[e] = params[e];
     __syncthreads();
     for (int64_t s0 = (int64_t)blockIdx.x * TILE; s0 < n; s0 += (int64_t)gridDim.x * TILE) {
-        mlp_tile_forward(P, X, s0, n, Xs, H1, H2, o);
+        mlp_tile_forward(P, X, nullptr, 0, s0, n, Xs, H1, H2, o);
         if (threadIdx.x < TILE && s0 + threadIdx.x < n) out[s0 + threadIdx.x] = o[threadIdx.x];
         __syncthreads();
     }
@@ -76,8 +77,9 @@ __global__ __launch_bounds__(MLP_NT) void k_mlp_forward(const float* __restrict_
 // tile by tile; per-block partial gradients are summed by k_mlp_reduce in a
 // fixed order, so results are reproducible.
 __global__ __launch_bounds__(MLP_NT) void k_mlp_grad(const float* __restrict__ params, const float* __restrict__ X,
-                                                     const float* __restrict__ Y, int64_t n, float inv_n,
-                                                     float* __restrict__ part_g, double* __restrict__ part_l) {
+                                                     const float* __restrict__ Y, const int64_t* __restrict__ perm,
+                                                     int64_t off, int64_t n, float inv_n, float* __restrict__ part_g,
+                                                     double* __restrict__ part_l) {
     __shared__ float P[NPARAM];
     __shared__ float Xs[TILE * NIN], H1[TILE * H], H2[TILE * H], D1[TILE * H], o[TILE], dout[TILE];
     __shared__ double lsum[TILE];
@@ -89,12 +91,12 @@ __global__ __launch_bounds__(MLP_NT) void k_mlp_grad(const float* __restrict__ p
     double lacc = 0.0;
     __syncthreads();
     for (int64_t s0 = (int64_t)blockIdx.x * TILE; s0 < n; s0 += (int64_t)gridDim.x * TILE) {
-        mlp_tile_forward(P, X, s0, n, Xs, H1, H2, o);
+        mlp_tile_forward(P, X, perm, off, s0, n, Xs, H1, H2, o);
         if (t < TILE) {
             const int64_t s = s0 + t;
             float d = 0.0f;
             if (s < n) {
-                const float z = o[t], y = Y[s];
+                const float z = o[t], y = Y[perm ? perm[off + s] : off + s];
                 lacc += (double)(fmaxf(z, 0.0f) - z * y + log1pf(expf(-fabsf(z))));
                 const float sig = 1.0f / (1.0f + expf(-z));
                 d = (sig - y) * inv_n;
@@ -233,13 +235,15 @@ struct chf_mlp_s {
     int64_t step = 0;
 };
 
+static void adam_step(chf_mlp_s& net, float lr, float beta1, float beta2, float eps, hipStream_t stream);
+
 static void mlp_grad_impl(chf_mlp_s& net, const float* feats, const float* labels, int64_t n, float* grad_out,
-                          double* loss_host, hipStream_t s) {
+                          double* loss_host, hipStream_t s, const int64_t* perm = nullptr, int64_t off = 0) {
     CHF_CHECK(n >= 1, CHF_EINVAL, "need at least one sample");
     const int64_t tiles = (n + TILE - 1) / TILE;
     const int grid = (int)std::min<int64_t>(MLP_GRID, tiles);
-    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(MLP_NT), 0, s, net.w.p, feats, labels, n, (float)(1.0 / n),
-                       net.part_g.p, net.part_l.p);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(MLP_NT), 0, s, net.w.p, feats, labels, perm, off, n,
+                       (float)(1.0 / n), net.part_g.p, net.part_l.p);
     CHF_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_mlp_reduce, dim3((NPARAM + 255) / 256), dim3(256), 0, s, net.part_g.p, net.part_l.p, grid,
                        1.0 / n, grad_out, net.part_l.p + MLP_GRID);
@@ -309,13 +313,62 @@ extern "C" int chf_mlp_train_step(chf_mlp net, const float* feats, const float* 
                   "bad optimiser parameters");
         double l = 0.0;
         mlp_grad_impl(*net, feats, labels, n, net->g.p, loss_host ? &l : nullptr, stream);
-        net->step += 1;
-        const float bc1 = 1.0f - std::pow(beta1, (float)net->step);
-        const float bc2 = 1.0f - std::pow(beta2, (float)net->step);
-        hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, stream, net->w.p, (const float*)net->g.p,
-                           net->m.p, net->v.p, lr, beta1, beta2, eps, bc1, bc2);
-        CHF_LAUNCH_CHECK();
+        adam_step(*net, lr, beta1, beta2, eps, stream);
         if (loss_host) *loss_host = (float)l;
+    });
+}
+
+static void adam_step(chf_mlp_s& net, float lr, float beta1, float beta2, float eps, hipStream_t stream) {
+    net.step += 1;
+    const float bc1 = 1.0f - std::pow(beta1, (float)net.step);
+    const float bc2 = 1.0f - std::pow(beta2, (float)net.step);
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, stream, net.w.p, (const float*)net.g.p,
+                       net.m.p, net.v.p, lr, beta1, beta2, eps, bc1, bc2);
+    CHF_LAUNCH_CHECK();
+}
+
+extern "C" int chf_mlp_train(chf_mlp net, const float* feats, const float* labels, int64_t n, const int64_t* perm,
+                             int64_t batch, int epochs, float lr, float beta1, float beta2, float eps,
+                             float* loss_hist, hipStream_t stream) {
+    return guarded([&] {
+        CHF_CHECK(net && feats && labels && n >= 1 && batch >= 1 && epochs >= 0, CHF_EINVAL, "bad argument");
+        CHF_CHECK(lr > 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0, CHF_EINVAL,
+                  "bad optimiser parameters");
+        for (int ep = 0; ep < epochs; ++ep) {
+            double lsum = 0.0;
+            int64_t seen = 0;
+            for (int64_t off = 0; off < n; off += batch) {
+                const int64_t nb = std::min(batch, n - off);
+                double l = 0.0;
+                const bool want = loss_hist != nullptr;
+                mlp_grad_impl(*net, feats, labels, nb, net->g.p, want ? &l : nullptr, stream, perm, off);
+                adam_step(*net, lr, beta1, beta2, eps, stream);
+                lsum += l * nb;
+                seen += nb;
+            }
+            if (loss_hist) loss_hist[ep] = (float)(lsum / seen);
+        }
+        CHF_HIP(hipStreamSynchronize(stream));
+    });
+}
+
+extern "C" int chf_mlp_labels(chf_bsr A, chf_pattern P, float* labels, hipStream_t stream) {
+    return guarded([&] {
+        CHF_CHECK(A && P && labels, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(P->nb == A->nb, CHF_EINVAL, "pattern and matrix sizes differ");
+        std::vector<int64_t> crow;
+        std::vector<int32_t> ccol;
+        a2_candidates(A, crow, ccol);
+        std::vector<float> h(ccol.size(), 0.0f);
+        for (int64_t k = 0; k < A->nb; ++k) {
+            const int32_t* pb = P->colidx.data() + P->rowptr[k];
+            const int32_t* pe = P->colidx.data() + P->rowptr[k + 1];
+            for (int64_t e = crow[k]; e < crow[k + 1]; ++e) h[e] = std::binary_search(pb, pe, ccol[e]) ? 1.0f : 0.0f;
+        }
+        if (!h.empty()) {
+            CHF_HIP(hipMemcpyAsync(labels, h.data(), h.size() * 4, hipMemcpyHostToDevice, stream));
+            CHF_HIP(hipStreamSynchronize(stream));
+        }
     });
 }
 

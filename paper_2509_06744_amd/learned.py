@@ -1,0 +1,51 @@
+"""Learned pattern proposer driver: assembles training sets and trains the
+network through the C ABI (features, labels, training and proposal all run
+in the library's kernels; torch only holds device buffers)."""
+from __future__ import annotations
+
+import torch
+
+from . import binding as chf
+
+
+def dataset(items, device="cuda"):
+    """items: iterable of (A, nx, ny, P) with P the target pattern (Algorithm
+    1's). Returns (features float32 [n, 4], labels float32 [n]) on the device."""
+    feats, labels = [], []
+    for A, nx, ny, P in items:
+        rowptr, _ = chf.mlp_candidates(A)
+        n = int(rowptr[-1])
+        f = torch.empty(n * 4, dtype=torch.float32, device=device)
+        y = torch.empty(n, dtype=torch.float32, device=device)
+        chf.mlp_features(A, nx, ny, f)
+        chf.mlp_labels(A, P, y)
+        feats.append(f)
+        labels.append(y)
+    return torch.cat(feats).view(-1, 4), torch.cat(labels)
+
+
+def train(X, Y, params0, perm, epochs=4, batch=8192, lr=2e-3):
+    """Mini-batch Adam over the rows of (X, Y) in the order of `perm`."""
+    net = chf.mlp_create(params0)
+    hist = chf.mlp_train(net, X, Y, Y.shape[0], perm, batch=batch, epochs=epochs, lr=lr)
+    return net, hist
+
+
+def energy_factor(L, A, e0, tol=1e-8, maxit=50):
+    """V-cycle convergence factor in the energy norm: iterate e <- V(0, e)
+    until ||e||_A < tol ||e0||_A or maxit cycles; returns (rho_A, cycles)."""
+    e = e0.clone()
+    zero = torch.zeros_like(e)
+    ae = torch.empty_like(e)
+    chf.bsr_spmv(A, e, ae)
+    en0 = float(torch.dot(e, ae))
+    en = en0
+    n = 0
+    while n < maxit:
+        chf.vcycle(L, zero, e, x_is_zero=False)
+        n += 1
+        chf.bsr_spmv(A, e, ae)
+        en = float(torch.dot(e, ae))
+        if (en / en0) ** 0.5 < tol:
+            break
+    return (en / en0) ** (1.0 / (2 * n)), n

@@ -19,5 +19,6 @@ from .generator import (  # noqa: F401
     uniform_start,
     grid_sizes,
     mlp_init,
+    permutation,
 )
 from .configs import CONFIGS, ProblemConfig  # noqa: F401

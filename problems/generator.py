@@ -227,3 +227,8 @@ def mlp_init(seed: int) -> np.ndarray:
     w2 = rng.uniform(-1, 1, (64, 64)) * np.sqrt(6.0 / 64)
     w3 = rng.uniform(-1, 1, 64) * np.sqrt(6.0 / 64)
     return np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, [0.0]]).astype(np.float32)
+
+
+def permutation(seed: int, n: int) -> np.ndarray:
+    """Seeded random permutation of n training rows."""
+    return np.random.default_rng(np.random.SeedSequence([seed, 271828])).permutation(n).astype(np.int64)

@@ -44,7 +44,7 @@ def oracle_levels(p, levels, mode="lower", tmax=0, seed=0, **kw):
     return solver.build_levels(from_problem(p), pro, starts, mode, tmax, bases=level_basis(p, levels), **kw)
 
 
-def gpu_levels(p, levels, degree, pattern, tmax=0, dtype=0, seed=0, betas=None):
+def gpu_levels(p, levels, degree, pattern, tmax=0, dtype=0, seed=0, betas=None, level0_pattern=None):
     """Build the GPU hierarchy for problem p through the C ABI."""
     import paper_2509_06744_amd as chf
     A = upload(p)
@@ -54,6 +54,8 @@ def gpu_levels(p, levels, degree, pattern, tmax=0, dtype=0, seed=0, betas=None):
         ps = ps.tocsr()
         chf.levels_add_coarse(L, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
     v0 = None if betas is not None else [dev(s) for s in starts[:-1]]
+    if level0_pattern is not None:
+        chf.levels_set_pattern(L, 0, level0_pattern)
     chf.levels_setup(L, degree=degree, pattern=pattern, tmax=tmax, dtype=dtype, v0=v0)
     if betas is not None:
         for l, bt in enumerate(betas):
