@@ -94,31 +94,60 @@ __device__ bool small_chol(const double* H, double* LH, int b, int lane, int* fl
     return true;
 }
 
-// Gains for candidates cand[s0 .. s0+cnt) (cnt <= NB). Ybuf: global, row i of
-// the right-hand-side block at Ybuf[i * 64 + lane]. On return gain[] is set
-// (for with_gain) and R.W/Hc/U hold L_W, H_kc, L_W^{-1} H_kc^T per group.
+// Gains for candidates cand[s0 .. s0+cnt) (cnt <= NB), b <= MAXB. Lane
+// (ci, col) owns column col of candidate ci's right-hand-side block
+// A[P~, c]; the block is kept at Ybuf[i * NT + lane] (row i). On return
+// gain[] is set (when non-null) and R.W / R.U hold L_W and L_W^{-1} H_kc^T
+// for each candidate of the batch.
+template <int MAXB, int NT>
 __device__ void ad_batch(int k, int b, int NB, int m, int M, const int* plist, const int* cand, int s0, int cnt,
                          const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                          const double* __restrict__ a_vals, const AdRegion& R, double* __restrict__ Ybuf,
-                         double* gain, int* flag, int* err) {
+                         double* gain, double* part, int* flag, int* err) {
+    // NB = (NT / 64) * (64 / b) candidates per batch: every wavefront holds
+    // 64 / b groups of b lanes, one group per candidate.
     const int lane = threadIdx.x;
     const int bb = b * b;
-    const int ci = lane / b;
-    const int col = lane - ci * b;
-    const bool act = ci < cnt && lane < NB * b;
+    const int gw = 64 / b;
+    const int wl = lane & 63;
+    const int ci = (lane >> 6) * gw + wl / b;
+    const int col = wl - (wl / b) * b;
+    const int gl0 = lane - col;                  // first lane of this lane's group
+    const bool act = ci < cnt && wl < gw * b;
     const int c = act ? cand[s0 + ci] : 0;
-    // right-hand side A[P~, c][:, col], then forward substitution in place
     if (act) {
+        // right-hand side A[P~, c][:, col]
         for (int jb = 0; jb < m; ++jb) {
             const int e = find_block(a_rowptr, a_col, plist[jb], c);
             for (int r = 0; r < b; ++r)
-                Ybuf[(int64_t)(jb * b + r) * 64 + lane] = e >= 0 ? a_vals[(int64_t)e * bb + r * b + col] : 0.0;
+                Ybuf[(int64_t)(jb * b + r) * NT + lane] = e >= 0 ? a_vals[(int64_t)e * bb + r * b + col] : 0.0;
         }
-        for (int i = 0; i < M; ++i) {
-            const double* li = R.L + atri(i);
-            double s = Ybuf[(int64_t)i * 64 + lane];
-            for (int j = 0; j < i; ++j) s -= li[j] * Ybuf[(int64_t)j * 64 + lane];
-            Ybuf[(int64_t)i * 64 + lane] = s / li[i];
+        // Y_c = L^{-1} A[P~, c], right-looking by block rows: the b solved
+        // values of a block stay in registers and every later row is updated
+        // independently of the others.
+        for (int jb = 0; jb < m; ++jb) {
+            const int i0 = jb * b;
+            double yv[MAXB];
+#pragma unroll
+            for (int r = 0; r < MAXB; ++r) {
+                if (r < b) {
+                    const double* li = R.L + atri(i0 + r) + i0;
+                    double sacc = Ybuf[(int64_t)(i0 + r) * NT + lane];
+#pragma unroll
+                    for (int q = 0; q < MAXB; ++q)
+                        if (q < r) sacc -= li[q] * yv[q];
+                    yv[r] = sacc / li[r];
+                    Ybuf[(int64_t)(i0 + r) * NT + lane] = yv[r];
+                }
+            }
+            for (int i = i0 + b; i < M; ++i) {
+                const double* li = R.L + atri(i) + i0;
+                double sacc = Ybuf[(int64_t)i * NT + lane];
+#pragma unroll
+                for (int q = 0; q < MAXB; ++q)
+                    if (q < b) sacc -= li[q] * yv[q];
+                Ybuf[(int64_t)i * NT + lane] = sacc;
+            }
         }
     }
     __syncthreads();
@@ -126,18 +155,34 @@ __device__ void ad_batch(int k, int b, int NB, int m, int M, const int* plist, c
     if (act) {
         const int ekc = find_block(a_rowptr, a_col, k, c);
         const int ecc = find_block(a_rowptr, a_col, c, c);
+        double h[MAXB], w[MAXB];
+#pragma unroll
+        for (int rr = 0; rr < MAXB; ++rr) {
+            if (rr < b) {
+                h[rr] = ekc >= 0 ? a_vals[(int64_t)ekc * bb + rr * b + col] : 0.0;
+                w[rr] = ecc >= 0 ? a_vals[(int64_t)ecc * bb + rr * b + col] : 0.0;
+            }
+        }
+        for (int i = 0; i < M; ++i) {
+            const double yi = Ybuf[(int64_t)i * NT + lane];
+            const double* yk = R.Yk + (int64_t)i * b;
+            const double* yg = Ybuf + (int64_t)i * NT + gl0;
+#pragma unroll
+            for (int rr = 0; rr < MAXB; ++rr) {
+                if (rr < b) {
+                    h[rr] -= yk[rr] * yi;
+                    w[rr] -= yg[rr] * yi;
+                }
+            }
+        }
         double* Hc = R.Hc + ci * bb;
         double* W = R.W + ci * bb;
-        for (int rr = 0; rr < b; ++rr) {
-            double h = ekc >= 0 ? a_vals[(int64_t)ekc * bb + rr * b + col] : 0.0;
-            double w = ecc >= 0 ? a_vals[(int64_t)ecc * bb + rr * b + col] : 0.0;
-            for (int i = 0; i < M; ++i) {
-                const double yi = Ybuf[(int64_t)i * 64 + lane];
-                h -= R.Yk[(int64_t)i * b + rr] * yi;
-                w -= Ybuf[(int64_t)i * 64 + ci * b + rr] * yi;
+#pragma unroll
+        for (int rr = 0; rr < MAXB; ++rr) {
+            if (rr < b) {
+                Hc[rr * b + col] = h[rr];
+                W[rr * b + col] = w[rr];
             }
-            Hc[rr * b + col] = h;
-            W[rr * b + col] = w;
         }
     }
     if (lane == 0) *flag = 1;
@@ -167,9 +212,9 @@ __device__ void ad_batch(int k, int b, int NB, int m, int M, const int* plist, c
         const double* Hc = R.Hc + ci * bb;
         double* U = R.U + ci * bb;
         for (int i = 0; i < b; ++i) {
-            double s = Hc[col * b + i];
-            for (int q = 0; q < i; ++q) s -= W[i * b + q] * U[q * b + col];
-            U[i * b + col] = s / W[i * b + i];
+            double sacc = Hc[col * b + i];
+            for (int q = 0; q < i; ++q) sacc -= W[i * b + q] * U[q * b + col];
+            U[i * b + col] = sacc / W[i * b + i];
         }
     }
     __syncthreads();
@@ -178,61 +223,70 @@ __device__ void ad_batch(int k, int b, int NB, int m, int M, const int* plist, c
         const double* U = R.U + ci * bb;
         double* X = R.X + ci * bb;
         for (int j = 0; j < b; ++j) {
-            double s = U[col * b + j];
-            for (int q = 0; q < j; ++q) s -= X[col * b + q] * R.LH[j * b + q];
-            X[col * b + j] = s / R.LH[j * b + j];
+            double sacc = U[col * b + j];
+            for (int q = 0; q < j; ++q) sacc -= X[col * b + q] * R.LH[j * b + q];
+            X[col * b + j] = sacc / R.LH[j * b + j];
         }
     }
     __syncthreads();
-    // C = X X^T: row `col`
+    // N = C = X X^T: row `col`
     if (act) {
         const double* X = R.X + ci * bb;
         double* Cm = R.Cm + ci * bb;
         for (int j = 0; j < b; ++j) {
-            double s = 0.0;
-            for (int q = 0; q < b; ++q) s += X[col * b + q] * X[j * b + q];
-            Cm[col * b + j] = s;
+            double sacc = 0.0;
+            for (int q = 0; q < b; ++q) sacc += X[col * b + q] * X[j * b + q];
+            Cm[col * b + j] = sacc;
         }
     }
     __syncthreads();
-    // g = -log det(I - C): Cholesky of I - C with pivots 1 - s_i, logged by log1p
-    if (act && col == 0) {
-        double* Cm = R.Cm + ci * bb;   // overwritten by the factor's strict lower part
-        double* lo = R.X + ci * bb;    // X is no longer needed
-        double out = 0.0;
-        bool ok = true;
-        for (int i = 0; i < b && ok; ++i) {
-            for (int j = 0; j < i; ++j) {
-                double s = -Cm[i * b + j];
-                for (int q = 0; q < j; ++q) s -= lo[i * b + q] * lo[j * b + q];
-                lo[i * b + j] = s / lo[j * b + j];
-            }
-            double s = Cm[i * b + i];
-            for (int q = 0; q < i; ++q) s += lo[i * b + q] * lo[i * b + q];
-            if (!(s < 1.0)) { ok = false; break; }
-            lo[i * b + i] = sqrt(1.0 - s);
-            out += log1p(-s);
+    // g = -log det(I - C): right-looking Cholesky of I - C written on
+    // N = C + sum_q l_q l_q^T, whose diagonal is s_q = 1 - pivot_q^2, so each
+    // pivot's log is log1p(-s_q); lanes of a group own rows.
+    double lg = 0.0;
+    for (int q = 0; q < b; ++q) {
+        double* N = R.Cm + ci * bb;
+        if (act && col == q) {
+            const double sq = N[q * b + q];
+            if (!(sq < 1.0)) *flag = 0;
+            lg += log1p(-sq);
+            N[q * b + q] = sqrt(fmax(1.0 - sq, 0.0));
         }
-        if (!ok) { *flag = 0; atomicMin(err, k); }
-        if (gain) gain[s0 + ci] = -out;
+        __syncthreads();
+        if (act && col > q) N[col * b + q] = -N[col * b + q] / N[q * b + q];
+        __syncthreads();
+        if (act && col > q)
+            for (int j = q + 1; j <= col; ++j) N[col * b + j] += N[col * b + q] * N[j * b + q];
+        __syncthreads();
+    }
+    part[lane] = lg;
+    __syncthreads();
+    if (!*flag) {
+        if (lane == 0) atomicMin(err, k);
+        return;
+    }
+    if (act && col == 0 && gain) {
+        double acc = 0.0;
+        for (int q = 0; q < b; ++q) acc += part[lane + q];
+        gain[s0 + ci] = -acc;
     }
     __syncthreads();
 }
 
-template <bool LDSMODE>
+template <int MAXB, int NT>
 __device__ void ad_row(int k, int b, int tmax, double thresh, const int* __restrict__ a_rowptr,
                        const int* __restrict__ a_col, const double* __restrict__ a_vals, int* __restrict__ out_cols,
                        int* __restrict__ out_cnt, double* base, double* __restrict__ Ybuf, int* plist, int* cand,
-                       double* gain, int* sh, int* err) {
+                       double* gain, double* part, int* sh, int* err) {
     const int lane = threadIdx.x;
-    const int NB = 64 / b;
-    const int Mmax = tmax * b;
+    const int NB = (NT / 64) * (64 / b);
+    const int Mmax = (tmax - 1) * b;   // L, Y_k and Y_c never grow past t_max - 1 blocks
     const int bb = b * b;
     AdRegion R = ad_region(base, Mmax, b, NB);
     // sh[0] = ncand, sh[1] = m, sh[2] = c*, sh[3] = flag, sh[4] = continue
     // init: H_kk = A_kk, candidates = pattern of A_k left of the diagonal
     const int ekk = find_block(a_rowptr, a_col, k, k);
-    for (int e = lane; e < bb; e += 64) R.Hkk[e] = ekk >= 0 ? a_vals[(int64_t)ekk * bb + e] : 0.0;
+    for (int e = lane; e < bb; e += NT) R.Hkk[e] = ekk >= 0 ? a_vals[(int64_t)ekk * bb + e] : 0.0;
     if (lane == 0) {
         int nc = 0;
         for (int e = a_rowptr[k]; e < a_rowptr[k + 1]; ++e) {
@@ -253,8 +307,8 @@ __device__ void ad_row(int k, int b, int tmax, double thresh, const int* __restr
         const int M = m * b;
         if (nc == 0) break;
         for (int s0 = 0; s0 < nc; s0 += NB) {
-            ad_batch(k, b, NB, m, M, plist, cand, s0, min(NB, nc - s0), a_rowptr, a_col, a_vals, R, Ybuf, gain,
-                     sh + 3, err);
+            ad_batch<MAXB, NT>(k, b, NB, m, M, plist, cand, s0, min(NB, nc - s0), a_rowptr, a_col, a_vals, R, Ybuf,
+                               gain, part, sh + 3, err);
             if (!sh[3]) { ok = false; break; }
         }
         if (!ok) break;
@@ -272,20 +326,30 @@ __device__ void ad_row(int k, int b, int tmax, double thresh, const int* __restr
         __syncthreads();
         if (!sh[4]) break;
         const int bi = sh[2];
+        if (t == tmax - 1) {
+            // last step: the pattern grows, nothing else is needed afterwards
+            if (lane == 0) {
+                plist[m] = cand[bi];
+                sh[1] = m + 1;
+            }
+            __syncthreads();
+            break;
+        }
         // recompute Y, L_W and U for c* alone (group 0)
-        ad_batch(k, b, NB, m, M, plist, cand, bi, 1, a_rowptr, a_col, a_vals, R, Ybuf, nullptr, sh + 3, err);
+        ad_batch<MAXB, NT>(k, b, NB, m, M, plist, cand, bi, 1, a_rowptr, a_col, a_vals, R, Ybuf, nullptr, part,
+                           sh + 3, err);
         if (!sh[3]) { ok = false; break; }
         // extend L by [Y_c*^T, L_W], Y_k by U, H_kk -= U^T U
-        for (int t2 = lane; t2 < b * (M + b); t2 += 64) {
+        for (int t2 = lane; t2 < b * (M + b); t2 += NT) {
             int r = t2 / (M + b), i = t2 - r * (M + b);
             double v;
-            if (i < M) v = Ybuf[(int64_t)i * 64 + r];
+            if (i < M) v = Ybuf[(int64_t)i * NT + r];
             else v = (i - M <= r) ? R.W[r * b + (i - M)] : 0.0;
             if (i <= M + r) R.L[atri(M + r) + i] = v;
         }
-        for (int e = lane; e < bb; e += 64) R.Yk[(int64_t)M * b + e] = R.U[e];
+        for (int e = lane; e < bb; e += NT) R.Yk[(int64_t)M * b + e] = R.U[e];
         __syncthreads();
-        for (int e = lane; e < bb; e += 64) {
+        for (int e = lane; e < bb; e += NT) {
             int r = e / b, s = e - r * b;
             double acc = 0.0;
             for (int q = 0; q < b; ++q) acc += R.U[q * b + r] * R.U[q * b + s];
@@ -340,31 +404,31 @@ __device__ void ad_row(int k, int b, int tmax, double thresh, const int* __restr
     __syncthreads();
 }
 
-__global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, double thresh,
+template <int MAXB, int NT>
+__global__ __launch_bounds__(NT) void k_adaptive(int64_t nb, int b, int tmax, double thresh,
                                                  const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                                  const double* __restrict__ a_vals, int* __restrict__ out_cols,
-                                                 int* __restrict__ out_cnt, int use_lds, double* scratch,
-                                                 int64_t region_stride, int* counter, int* err) {
+                                                 int* __restrict__ out_cnt, int region_lds, int ybuf_lds,
+                                                 int64_t region_doubles, double* scratch, int64_t gstride,
+                                                 int* counter, int* err) {
     extern __shared__ double lds[];
     __shared__ int plist[AD_MAXP];
     __shared__ int cand[AD_MAXC];
     __shared__ double gain[AD_MAXC];
     __shared__ int sh[8];
     __shared__ int next;
-    double* greg = scratch + (int64_t)blockIdx.x * region_stride;
-    double* Ybuf = greg + (use_lds ? 0 : ad_region_doubles(tmax * b, b, 64 / b));
+    __shared__ double part[NT];
+    double* greg = scratch + (int64_t)blockIdx.x * gstride;
+    double* reg = region_lds ? lds : greg;
+    double* Ybuf = ybuf_lds ? lds + (region_lds ? region_doubles : 0) : greg + (region_lds ? 0 : region_doubles);
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
         const int64_t row = next;
         __syncthreads();
         if (row >= nb) break;
-        if (use_lds)
-            ad_row<true>((int)row, b, tmax, thresh, a_rowptr, a_col, a_vals, out_cols, out_cnt, lds, Ybuf, plist,
-                         cand, gain, sh, err);
-        else
-            ad_row<false>((int)row, b, tmax, thresh, a_rowptr, a_col, a_vals, out_cols, out_cnt, greg, Ybuf,
-                          plist, cand, gain, sh, err);
+        ad_row<MAXB, NT>((int)row, b, tmax, thresh, a_rowptr, a_col, a_vals, out_cols, out_cnt, reg, Ybuf, plist, cand,
+                     gain, part, sh, err);
     }
 }
 
@@ -383,28 +447,48 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
         }
         return P.release();
     }
-    const int NB = 64 / b;
-    const int Mmax = tmax * b;
+    constexpr int NT = 64;   // one wavefront per row: wider workgroups lose more to barriers than they gain
+    const int NB = (NT / 64) * (64 / b);
+    const int Mmax = (tmax - 1) * b;
     const int64_t region = ad_region_doubles(Mmax, b, NB);
     const size_t region_bytes = (size_t)region * 8;
+    const size_t ybuf_bytes = (size_t)Mmax * NT * 8;
     int dev = 0, lim = 0;
     CHF_HIP(hipGetDevice(&dev));
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t static_lds = AD_MAXP * 4 + AD_MAXC * 12 + 64;
-    const bool use_lds = region_bytes + static_lds <= (size_t)std::min(lim, 64 * 1024);
+    const size_t static_lds = AD_MAXP * 4 + AD_MAXC * 12 + 64 + NT * 8;
+    const size_t avail = (size_t)lim > static_lds + 512 ? (size_t)lim - static_lds - 512 : 0;
+    // placement: everything in LDS if it fits, else the right-hand-side buffer
+    // (the operand of the forward substitutions) in LDS, else both in a global slot
+    // LDS only while at least 4 workgroups still fit on a CU: occupancy
+    // matters more than latency for this kernel (measured at 512^2, b = 10:
+    // t_max 8 takes 1.19 s with everything in a global slot at 8 workgroups
+    // per CU, 1.74 s with the right-hand sides in LDS at 3 per CU)
+    const size_t occ = (size_t)lim / 4 > static_lds + 512 ? (size_t)lim / 4 - static_lds - 512 : 0;
+    bool region_lds = region_bytes + ybuf_bytes <= occ;
+    bool ybuf_lds = region_lds || ybuf_bytes <= occ;
+    if (const char* env = std::getenv("CHF_ADAPTIVE_PLACEMENT")) {   // tuning knob: "global" or "region"
+        if (std::string(env) == "global") region_lds = ybuf_lds = false;
+        if (std::string(env) == "region" && region_bytes <= avail) { region_lds = true; ybuf_lds = false; }
+    }
+    const size_t dyn = (region_lds ? region_bytes : 0) + (ybuf_lds && !region_lds ? ybuf_bytes : 0) +
+                       (region_lds && ybuf_lds ? ybuf_bytes : 0);
     const int cus = device_cu_count();
-    const size_t per_wg_lds = (use_lds ? region_bytes : 0) + static_lds;
-    const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (160 * 1024) / (per_wg_lds + 256)));
+    const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / (dyn + static_lds + 512)));
     const int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, nb);
-    const int64_t stride = (use_lds ? 0 : region) + (int64_t)Mmax * 64;
+    const int64_t stride = std::max<int64_t>(1, (region_lds ? 0 : region) + (ybuf_lds ? 0 : (int64_t)Mmax * NT));
     DevBuf<double> scratch((size_t)grid * stride);
+    CHF_CHECK(b <= 32, CHF_EINVAL, "adaptive pattern supports block sizes up to 32");
+    auto kern = b == 10 ? k_adaptive<10, NT> : b == 21 ? k_adaptive<21, NT> : k_adaptive<32, NT>;
+    if (dyn > 64 * 1024)
+        CHF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     DevBuf<int> out_cols((size_t)nb * (tmax + 1)), out_cnt(nb), flags(2);
     int init[2] = {0, INT32_MAX};
     flags.upload(init, 2, s);
     const double thresh = -std::log(tau) + AD_GAIN_EPS;
-    hipLaunchKernelGGL(k_adaptive, dim3((unsigned)grid), dim3(64), use_lds ? region_bytes : 0, s, nb, b, tmax, thresh,
-                       A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, out_cols.p, out_cnt.p, (int)use_lds, scratch.p,
-                       stride, flags.p, flags.p + 1);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), dyn, s, nb, b, tmax, thresh, A->d_rowptr.p,
+                       A->d_colidx.p, A->d_vals.p, out_cols.p, out_cnt.p, (int)region_lds, (int)ybuf_lds, region,
+                       scratch.p, stride, flags.p, flags.p + 1);
     CHF_LAUNCH_CHECK();
     std::vector<int> hcols((size_t)nb * (tmax + 1)), hcnt(nb);
     int hflags[2];
@@ -441,6 +525,7 @@ extern "C" int chf_pattern_adaptive(chf_bsr A, int tmax, double tau, chf_pattern
 // Algorithm 1.
 namespace chf {
 
+template <int MAXB>
 __global__ __launch_bounds__(64) void k_mlp_features(int64_t nb, int b, int nx, int ny,
                                                      const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                                      const double* __restrict__ a_vals,
@@ -473,8 +558,8 @@ __global__ __launch_bounds__(64) void k_mlp_features(int64_t nb, int b, int nx, 
         const int kx = (int)(k % nx), ky = (int)((k / nx) % ny), kz = (int)(k / ((int64_t)nx * ny));
         for (int s0 = 0; s0 < nc; s0 += NB) {
             const int cnt = min(NB, nc - s0);
-            ad_batch((int)k, b, NB, 0, 0, nullptr, cand, s0, cnt, a_rowptr, a_col, a_vals, R, base, gain, sh + 3,
-                     err);
+            ad_batch<MAXB, 64>((int)k, b, NB, 0, 0, nullptr, cand, s0, cnt, a_rowptr, a_col, a_vals, R, base, gain,
+                               part, sh + 3, err);
             if (!sh[3]) break;
             const int ci = lane / b, col = lane - ci * b;
             const bool act = ci < cnt && lane < NB * b;
@@ -570,7 +655,9 @@ void mlp_features_impl(chf_bsr A, int nx, int ny, const std::vector<int64_t>& cr
     err.upload(&init, 1, s);
     const int64_t grid = std::min<int64_t>((int64_t)device_cu_count() * 8, nb);
     DevBuf<double> scratch(1);
-    hipLaunchKernelGGL(k_mlp_features, dim3((unsigned)grid), dim3(64), region_bytes, s, nb, b, nx, ny, A->d_rowptr.p,
+    CHF_CHECK(b <= 32, CHF_EINVAL, "features support block sizes up to 32");
+    auto kern = b == 10 ? k_mlp_features<10> : b == 21 ? k_mlp_features<21> : k_mlp_features<32>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), region_bytes, s, nb, b, nx, ny, A->d_rowptr.p,
                        A->d_colidx.p, A->d_vals.p, d_crow.p, d_ccol.p, feats, scratch.p, (int64_t)0, err.p);
     CHF_LAUNCH_CHECK();
     int herr = 0;

@@ -195,7 +195,10 @@ static size_t lds_bytes(int nlds, int b) {
 static void launch_setup(int nt, const SetupArgs& a, hipStream_t s) {
     const int cus = device_cu_count();
     size_t shm = lds_bytes(a.nlds, a.b);
-    int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (160 * 1024) / (shm + 4096 + 64)));
+    int dev = 0, lim = 0;
+    CHF_HIP(hipGetDevice(&dev));
+    CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / (shm + 4096 + 64)));
     int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(1, a.nrows));
     int64_t stride = (int64_t)FSAI_MAXN * (FSAI_MAXN + 1) / 2 + (int64_t)FSAI_MAXN * a.b;
     // global scratch only when some row exceeds the LDS limit
@@ -207,6 +210,11 @@ static void launch_setup(int nt, const SetupArgs& a, hipStream_t s) {
         scr = scratch.p;
     }
     fill_zero(a.counter, sizeof(int), s);
+    if (shm > 64 * 1024) {
+        CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<128>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    }
     switch (nt) {
         case 64:
             hipLaunchKernelGGL(k_fsai_setup<64>, dim3(grid), dim3(64), shm, s, a.nrows, a.order, a.b, a.a_rowptr,
@@ -266,7 +274,7 @@ static int max_lds_n(int b) {
     int lim = 0;
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     // static LDS: index table + scalars
-    size_t avail = (size_t)std::min(lim, 64 * 1024) - (FSAI_MAXM * FSAI_MAXM * 4 + 64);
+    size_t avail = (size_t)lim - (FSAI_MAXM * FSAI_MAXM * 4 + 64);
     int n = FSAI_MAXN;
     while (n > 0 && lds_bytes(n, b) > avail) --n;
     return n;
