@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--degree", type=int, default=4)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-seeds", type=int, default=32, help="training seeds 1..S")
+    ap.add_argument("--test-seeds", type=int, default=2, help="test seeds 100..100+T-1 (up to 8)")
     ap.add_argument("--cpu-grid", type=int, default=32, help="patches per side of the oracle's timing sample")
     ap.add_argument("--only-spmv", action="store_true",
                     help="build A only and run the level-0 residual SpMV (for hardware-counter passes)")
@@ -109,6 +112,74 @@ def cpu_baseline(n, b, tmax, degree, target_s=10.0):
                    f"adaptive t_max={tmax}); {el:.1f} s timed; oracle set-up {setup_s:.1f} s untimed; "
                    f"host affinity {cores} cores, OMP_NUM_THREADS={threads}"),
     }
+
+
+def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
+    """Train the pattern proposer on Algorithm 1's patterns (seeds 1..S of the
+    2D 64x64 and 3D 12^3 generators, b = 10, t_max = 8), then compare it with
+    Algorithm 1 on the benchmark grid for seeds 100.. : time to form the
+    level-0 pattern, and the V(k,k) energy-norm convergence factor with that
+    pattern (coarser levels use Algorithm 1 in both cases)."""
+    from paper_2509_06744_amd import learned
+    from problems import lanczos_starts, level_basis, make_problem, mlp_init, permutation, uniform_start
+    t0 = time.perf_counter()
+    items, keep = [], []
+    for seed in range(1, args.train_seeds + 1):
+        for nn, dim in [(64, 2), (12, 3)]:
+            q = make_problem(nn, dim, b, 2, seed=seed)
+            Aq = chf.bsr_create(q.nb, q.b, q.rowptr, q.colidx, q.vals)
+            Pq = chf.pattern_adaptive(Aq, args.tmax)
+            items.append((Aq, nn, nn, Pq))
+            keep.append((Aq, Pq))
+    X, Y = learned.dataset(items)
+    t_data = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    perm = torch.from_numpy(permutation(0, Y.shape[0])).to(dev)
+    net, hist = learned.train(X, Y, mlp_init(0), perm, epochs=4, batch=8192, lr=2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del items, keep, X, Y
+    tests = []
+    for seed in range(100, 100 + min(8, args.test_seeds)):
+        q = make_problem(n, 2, b, 2, seed=seed)
+        Aq = chf.bsr_create(q.nb, q.b, q.rowptr, q.colidx, q.vals)
+        starts = lanczos_starts(seed, [s * s * b for s in [n >> l for l in range(L)]])
+        v0 = [torch.from_numpy(s_).to(dev) for s_ in starts[:-1]]
+        e0 = torch.from_numpy(uniform_start(seed, q.ndof)).to(dev)
+        qb = level_basis(q, L)
+        rec = {"seed": seed}
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Pa = chf.pattern_adaptive(Aq, args.tmax)
+        rec["pattern_ms_adaptive"] = round(1e3 * (time.perf_counter() - t), 2)
+        t = time.perf_counter()
+        Pl = chf.mlp_propose(Aq, net, n, n, args.tmax)
+        rec["pattern_ms_learned"] = round(1e3 * (time.perf_counter() - t), 2)
+        ra, ca = chf.pattern_export(Pa)
+        rl, cl = chf.pattern_export(Pl)
+        same = sum(1 for kk in range(q.nb) if np.array_equal(ca[ra[kk]:ra[kk + 1]], cl[rl[kk]:rl[kk + 1]]))
+        rec["rows_identical"] = round(same / q.nb, 4)
+        for name, P in [("adaptive", Pa), ("learned", Pl)]:
+            H = chf.levels_create(Aq)
+            for ps, basis in zip(pro, qb):
+                chf.levels_add_coarse(H, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
+            chf.levels_set_pattern(H, 0, P)
+            t = time.perf_counter()
+            chf.levels_setup(H, degree=k, pattern=1, tmax=args.tmax, v0=v0)
+            torch.cuda.synchronize()
+            rec[f"levels_setup_ms_{name}"] = round(1e3 * (time.perf_counter() - t), 1)
+            rho, cyc = learned.energy_factor(H, Aq, e0)
+            rec[f"rho_A_{name}"] = round(rho, 5)
+            rec[f"cycles_{name}"] = cyc
+            H.destroy()
+        tests.append(rec)
+        log(f"learned vs adaptive: {rec}")
+        del q
+    return {"train": {"seeds": f"1..{args.train_seeds}", "grids": "64x64 2D and 12^3 3D, b=10, t_max=8",
+                      "samples": int(len(perm)), "epochs": 4, "loss": [round(float(v), 5) for v in hist],
+                      "data_s": round(t_data, 2), "train_s": round(t_train, 2)},
+            "test": tests}
 
 
 def main():
@@ -292,6 +363,9 @@ def main():
         res["mixed_f32_over_fp64_time"] = round(res["mixed_f32"]["time_ms"] / res["fp64"]["time_ms"], 4)
         res["mixed_bf16g_over_fp64_time"] = round(res["mixed_bf16g"]["time_ms"] / res["fp64"]["time_ms"], 4)
         out["pcg"] = res
+
+    if not args.no_learned:
+        out["learned"] = learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases)
 
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")

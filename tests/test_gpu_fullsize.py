@@ -1,0 +1,120 @@
+"""Parity and properties at the full sizes of the workloads (as launched by
+bench.py): sampled rows against the oracle, properties that hold at any size,
+and PCG convergence to the targets."""
+import numpy as np
+import pytest
+
+from oracle import fsai
+from oracle.bsr import from_problem
+from problems import make_problem, rhs
+from tests.helpers import dev, gpu_levels, host, rel_err, upload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def chf():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2509_06744_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def c1(chf):
+    p = make_problem(512, 2, 10, 2, seed=0)
+    return p, from_problem(p), upload(p)
+
+
+def _rows(nb, n):
+    rng = np.random.default_rng(1)
+    edge = [0, 1, n - 1, n, n * n - 1, n * (n // 2) + n // 2]
+    return sorted(set(edge) | set(int(r) for r in rng.integers(0, nb, 30)))
+
+
+def test_c1_spmv_sampled_rows(chf, c1):
+    import torch
+    p, a, A = c1
+    x = np.random.default_rng(0).standard_normal(p.ndof)
+    y = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    chf.bsr_spmv(A, dev(x), y)
+    yh = host(y)
+    for k in _rows(p.nb, p.n):
+        want = sum(a.block(k, int(j)) @ x[int(j) * 10:(int(j) + 1) * 10] for j in a.cols(k))
+        assert rel_err(yh[k * 10:(k + 1) * 10], want) < 1e-13
+
+
+def test_c1_preconditioner_sampled_rows(chf, c1):
+    """z = G^T G r on sampled rows, with the oracle's own G rows (Def. 2.2)."""
+    import torch
+    p, a, A = c1
+    P = chf.pattern_adaptive(A, 8)
+    prow, pcol = chf.pattern_export(P)
+    G = chf.fsai_setup(A, P)
+    r = np.random.default_rng(2).standard_normal(p.ndof)
+    z = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    w = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    chf.fsai_apply(G, dev(r), z, w)
+    zh = host(z)
+    # rows k of G that touch column i: i in P_k
+    for i in _rows(p.nb, p.n)[:12]:
+        ks = sorted(set(int(k) for k in np.searchsorted(prow, np.nonzero(pcol == i)[0], side="right") - 1))
+        og = fsai.fsai_rows(a, ks, prow, pcol)
+        acc = np.zeros(10)
+        for k in ks:
+            row = list(pcol[prow[k]:prow[k + 1]])
+            gk = og[k]
+            t = sum(gk[q] @ r[row[q] * 10:(row[q] + 1) * 10] for q in range(len(row)))
+            acc += gk[row.index(i)].T @ t
+        assert rel_err(zh[i * 10:(i + 1) * 10], acc) < 1e-12
+
+
+def test_c1_diag_gagt_identity(chf, c1):
+    p, a, A = c1
+    P = chf.pattern_adaptive(A, 8)
+    prow, pcol = chf.pattern_export(P)
+    G = chf.fsai_setup(A, P)
+    g = chf.fsai_export(G, len(pcol), 10)
+    for k in _rows(p.nb, p.n):
+        row = [int(j) for j in pcol[prow[k]:prow[k + 1]]]
+        gk = g[prow[k]:prow[k + 1]]
+        s = sum(gk[u] @ a.block(row[u], row[v]) @ gk[v].T for u in range(len(row)) for v in range(len(row)))
+        assert np.abs(s - np.eye(10)).max() < 1e-11
+
+
+def test_c1_pcg_fp64_and_mixed(chf, c1):
+    """512x512, b = 10, 6 levels, adaptive t_max 8, V(4,4): FP64 PCG to 1e-8,
+    mixed FP32 and BF16-G within a few iterations of it."""
+    import torch
+    p, a, _ = c1
+    b_ = dev(rhs(0, p.ndof))
+    its = {}
+    for dt, flex in [(0, False), (1, True), (2, True)]:
+        A, L, _, _ = gpu_levels(p, 6, 4, 1, tmax=8, dtype=dt)
+        x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+        it, hist, tr, _ = chf.pcg_solve(L, b_, x, rtol=1e-8, maxit=200, flexible=flex)
+        assert hist[-1] <= 1e-8 and tr < 5e-8
+        its[dt] = it
+        if dt == 0:   # bit-reproducible
+            x2 = torch.zeros_like(x)
+            it2, _, _, _ = chf.pcg_solve(L, b_, x2, rtol=1e-8, maxit=200)
+            assert it2 == it and torch.equal(x, x2)
+    assert its[1] <= its[0] + 6 and its[2] <= its[0] + 10
+
+
+def test_c2_mixed_triharmonic_full_size(chf):
+    """256x256 patches, b = 21, D = L^3, 5 levels, adaptive t_max 8, A and G
+    in FP32 (and BF16 G), outer FP64 PCG to a recursive residual of 1e-10.
+    The patch-bilinear transfer is low order for a sixth-order operator, so
+    the cycle is not grid-independent (the oracle needs 17, 35, 74 iterations
+    at 16^2, 32^2, 64^2); a few hundred iterations are expected here."""
+    import torch
+    p = make_problem(256, 2, 21, 3, seed=0)
+    b_ = dev(rhs(0, p.ndof))
+    for dt in (1, 2):
+        A, L, _, _ = gpu_levels(p, 5, 4, 1, tmax=8, dtype=dt)
+        x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+        it, hist, tr, _ = chf.pcg_solve(L, b_, x, rtol=1e-10, maxit=3000, flexible=True)
+        print(f"c2 dtype {dt}: {it} iterations, recursive {hist[-1]:.2e}, true {tr:.2e}")
+        assert hist[-1] <= 1e-10
