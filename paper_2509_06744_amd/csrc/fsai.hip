@@ -10,6 +10,8 @@
 // They are obtained from L^T Z = E (E the last b columns of I), G_k = Z^T.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -125,16 +127,227 @@ __device__ void fsai_row(int64_t k, int b, const int* __restrict__ a_rowptr, con
     __syncthreads();
 }
 
+// ------------------------------------------------- tiled MFMA local solver --
+// For larger local systems (n > ntile, b <= 16) the factorisation works on
+// 16 x 16 tiles of the lower triangle, held in the workgroup's global scratch
+// slot (L2/MALL resident): per tile column, one wavefront factors the
+// diagonal tile in registers, one thread per (tile, row) solves the panel, and
+// the four wavefronts update the trailing tiles with FP64 MFMA
+// (v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
+// and receives D[4 r + l / 16][l % 16] in register r). The b right-hand sides
+// of L^T Z = E are solved by tile rows with MFMA accumulations. Padding rows
+// of the last tile are identity rows.
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ inline v4d mfma16(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+__device__ inline double* tile_at(double* base, int I, int J) { return base + ((int64_t)I * (I + 1) / 2 + J) * 256; }
+
+__device__ inline void tri_decode(int t, int& I, int& J) {
+    int i = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    while (i * (i + 1) / 2 > t) --i;
+    I = i;
+    J = t - i * (i + 1) / 2;
+}
+
+__device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
+                               const double* __restrict__ a_vals, const int64_t* __restrict__ p_rowptr,
+                               const int* __restrict__ p_col, double* __restrict__ g_vals, double* tiles,
+                               double* panel, double* Zl, double* part, int* idx, int* sh_flag, int* bad_row) {
+    constexpr int NT = 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t p0 = p_rowptr[k];
+    const int m = (int)(p_rowptr[k + 1] - p0);
+    const int n = m * b;
+    const int T = (n + 15) / 16;
+    const int* cols = p_col + p0;
+    for (int t = tid; t < m * m; t += NT) {
+        int a = t / m, c = t - a * m;
+        int e = -1;
+        if (c <= a) {
+            int row = cols[a], want = cols[c];
+            int lo = a_rowptr[row], hi = a_rowptr[row + 1];
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (a_col[mid] < want) lo = mid + 1; else hi = mid;
+            }
+            if (lo < a_rowptr[row + 1] && a_col[lo] == want) e = lo;
+        }
+        idx[t] = e;
+    }
+    __syncthreads();
+    const int ntiles = T * (T + 1) / 2;
+    for (int64_t e = tid; e < (int64_t)ntiles * 256; e += NT) {
+        int I, J;
+        tri_decode((int)(e >> 8), I, J);
+        const int rc = (int)(e & 255), r = rc >> 4, c = rc & 15;
+        const int i = 16 * I + r, j = 16 * J + c;
+        double v;
+        if (i < n && j < n) {
+            if (j > i) {
+                v = 0.0;
+            } else {
+                const int a = i / b, ra = i - a * b, cb = j / b, rcc = j - cb * b;
+                const int ee = idx[a * m + cb];
+                v = ee >= 0 ? a_vals[(int64_t)ee * b * b + ra * b + rcc] : 0.0;
+            }
+        } else {
+            v = (i == j) ? 1.0 : 0.0;
+        }
+        tiles[e] = v;
+    }
+    if (tid == 0) sh_flag[0] = 1;
+    __syncthreads();
+    for (int kt = 0; kt < T; ++kt) {
+        // (a) diagonal tile, one wavefront, rows in registers
+        if (wave == 0) {
+            double* Dt = tile_at(tiles, kt, kt);
+            const int r = lane & 15;
+            double row[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) row[c] = Dt[r * 16 + c];
+            bool ok = true;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const double dq = __shfl(row[q], q, 64);
+                ok = ok && (dq > 0.0) && isfinite(dq);
+                const double lqq = sqrt(fmax(dq, 1e-300));
+                const double lrq = (r > q) ? row[q] / lqq : (r == q ? lqq : 0.0);
+                row[q] = lrq;
+#pragma unroll
+                for (int j = q + 1; j < 16; ++j) {
+                    const double ljq = __shfl(lrq, j, 64);
+                    if (j <= r) row[j] -= lrq * ljq;
+                }
+            }
+            if (lane < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    const double v = c <= r ? row[c] : 0.0;
+                    panel[r * 16 + c] = v;
+                    Dt[r * 16 + c] = v;
+                }
+            }
+            if (lane == 0 && !ok) sh_flag[0] = 0;
+        }
+        __syncthreads();
+        if (!sh_flag[0]) break;
+        // (b) panel: L_ik = A_ik L_kk^{-T}, one thread per (tile, row)
+        for (int w = tid; w < (T - kt - 1) * 16; w += NT) {
+            const int ti = kt + 1 + w / 16, r = w & 15;
+            double* Tt = tile_at(tiles, ti, kt);
+            double x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[c] = Tt[r * 16 + c];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                double sacc = x[c];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (q < c) sacc -= x[q] * panel[c * 16 + q];
+                x[c] = sacc / panel[c * 16 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                Tt[r * 16 + c] = x[c];
+                panel[(ti - kt) * 256 + r * 16 + c] = x[c];
+            }
+        }
+        __syncthreads();
+        // (c) trailing tiles A_IJ -= L_Ik L_Jk^T, kt < J <= I < T, on MFMA
+        const int nt = T - kt - 1;
+        const int npairs = nt * (nt + 1) / 2;
+        for (int pidx = wave; pidx < npairs; pidx += 4) {
+            int ii, jj;
+            tri_decode(pidx, ii, jj);
+            double* Ct = tile_at(tiles, kt + 1 + ii, kt + 1 + jj);
+            v4d acc;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) acc[rr] = Ct[(4 * rr + (lane >> 4)) * 16 + (lane & 15)];
+            const double* Li = panel + (ii + 1) * 256;
+            const double* Lj = panel + (jj + 1) * 256;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double av = -Li[(lane & 15) * 16 + 4 * q + (lane >> 4)];
+                const double bv = Lj[(lane & 15) * 16 + 4 * q + (lane >> 4)];
+                acc = mfma16(av, bv, acc);
+            }
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) Ct[(4 * rr + (lane >> 4)) * 16 + (lane & 15)] = acc[rr];
+        }
+        __syncthreads();
+    }
+    if (!sh_flag[0]) {
+        if (tid == 0) atomicMin(bad_row, (int)k);
+        for (int64_t t = tid; t < (int64_t)m * b * b; t += NT) g_vals[p0 * b * b + t] = 0.0;
+        __syncthreads();
+        return;
+    }
+    // L^T Z = E (Z: 16T x 16, columns c < b carry the last b unit vectors)
+    for (int e = tid; e < T * 256; e += NT) {
+        const int i = e >> 4, c = e & 15;
+        Zl[e] = (c < b && i == n - b + c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int I = T - 1; I >= 0; --I) {
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        for (int J = I + 1 + wave; J < T; J += 4) {
+            const double* LJI = tile_at(tiles, J, I);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double av = LJI[(4 * q + (lane >> 4)) * 16 + (lane & 15)];          // L_JI^T
+                const double bv = Zl[(16 * J + 4 * q + (lane >> 4)) * 16 + (lane & 15)];  // Z_J
+                acc = mfma16(av, bv, acc);
+            }
+        }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) part[wave * 256 + (4 * rr + (lane >> 4)) * 16 + (lane & 15)] = acc[rr];
+        __syncthreads();
+        if (tid < 16) {
+            const int c = tid;
+            const double* LII = tile_at(tiles, I, I);
+            double z[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int o = r * 16 + c;
+                z[r] = Zl[(16 * I + r) * 16 + c] - (part[o] + part[256 + o] + part[512 + o] + part[768 + o]);
+            }
+#pragma unroll
+            for (int r = 15; r >= 0; --r) {
+                double sacc = z[r];
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    if (q > r) sacc -= LII[q * 16 + r] * z[q];
+                z[r] = sacc / LII[r * 16 + r];
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) Zl[(16 * I + r) * 16 + c] = z[r];
+        }
+        __syncthreads();
+    }
+    for (int64_t t = tid; t < (int64_t)m * b * b; t += NT) {
+        const int a = (int)(t / (b * b));
+        const int rem = (int)(t - (int64_t)a * b * b);
+        const int r = rem / b, c = rem - r * b;
+        g_vals[(p0 + a) * b * b + rem] = Zl[(a * b + c) * 16 + r];
+    }
+    __syncthreads();
+}
+
 // Persistent kernel: each workgroup pops rows (ordered by decreasing local
-// size) from a global counter until the queue is empty. Rows with n <= nlds
-// work in LDS, larger rows in the workgroup's slot of a global scratch area.
+// size) from a global counter until the queue is empty. Per row, by size:
+// the tiled MFMA solver (n > ntile, 256-wide workgroups, b <= 16), the
+// scalar solver in LDS (n <= nlds), or the scalar solver in the workgroup's
+// global scratch slot.
 template <int NT>
 __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t* __restrict__ order, int b,
                                                    const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                                    const double* __restrict__ a_vals,
                                                    const int64_t* __restrict__ p_rowptr, const int* __restrict__ p_col,
-                                                   double* __restrict__ g_vals, int nlds, double* scratch,
-                                                   int64_t scratch_stride, int* counter, int* bad_row) {
+                                                   double* __restrict__ g_vals, int nlds, int ntile, int tmaxtiles,
+                                                   double* scratch, int64_t scratch_stride, int* counter,
+                                                   int* bad_row) {
     extern __shared__ double lds[];
     __shared__ int idx[FSAI_MAXM * FSAI_MAXM];
     __shared__ double sh_scal[1];
@@ -152,6 +365,16 @@ __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t*
         if (it >= nrows) break;
         const int64_t k = order[it];
         const int n = (int)(p_rowptr[k + 1] - p_rowptr[k]) * b;
+        if constexpr (NT == 256) {
+            if (n > ntile && b <= 16) {
+                double* panel = lds;
+                double* Zl = panel + (int64_t)tmaxtiles * 256;
+                double* part = Zl + (int64_t)tmaxtiles * 256;
+                fsai_row_tiled(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, gK, panel, Zl, part, idx,
+                               sh_flag, bad_row);
+                continue;
+            }
+        }
         if (n <= nlds)
             fsai_row<NT>(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, lds_K, lds_Z, idx, sh_scal,
                          sh_flag, bad_row);
@@ -162,15 +385,20 @@ __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t*
 }
 
 // ------------------------------------------------------------ autotuning --
-// The workgroup width (64, 128 or 256 lanes) is chosen per (b, largest local
-// size) by timing the persistent kernel on a sample of the rows; the choice is
-// cached for the process.
+// A configuration is a workgroup width (64, 128, 256) and a size threshold
+// above which rows take the tiled MFMA path (256-wide only). The best one for
+// (b, largest local size) is picked by timing the persistent kernel on an
+// evenly strided sample of the rows, and cached for the process.
 struct TuneKey {
     int b, nmax;
     bool operator<(const TuneKey& o) const { return b != o.b ? b < o.b : nmax < o.nmax; }
 };
-static std::map<TuneKey, int> g_tuned;
+struct TuneVal {
+    int nt, ntile;
+};
+static std::map<TuneKey, TuneVal> g_tuned;
 static std::mutex g_tune_mu;
+constexpr int NO_TILES = 1 << 30;
 
 struct SetupArgs {
     int64_t nrows;
@@ -192,20 +420,24 @@ static size_t lds_bytes(int nlds, int b) {
     return ((size_t)nlds * (nlds + 1) / 2 + (size_t)nlds * b) * sizeof(double);
 }
 
-static void launch_setup(int nt, const SetupArgs& a, hipStream_t s) {
+static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s) {
     const int cus = device_cu_count();
+    const bool tiled = cfg.nt == 256 && a.b <= 16 && a.nmax > cfg.ntile;
+    const int tmaxtiles = (a.nmax + 15) / 16;
     size_t shm = lds_bytes(a.nlds, a.b);
+    if (tiled) shm = std::max(shm, ((size_t)tmaxtiles * 256 * 2 + 4 * 256) * sizeof(double));
     int dev = 0, lim = 0;
     CHF_HIP(hipGetDevice(&dev));
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / (shm + 4096 + 64)));
     int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(1, a.nrows));
     int64_t stride = (int64_t)FSAI_MAXN * (FSAI_MAXN + 1) / 2 + (int64_t)FSAI_MAXN * a.b;
-    // global scratch only when some row exceeds the LDS limit
+    if (tiled) stride = std::max<int64_t>(stride, (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256);
+    // global scratch only when some row exceeds the LDS limit or is tiled
     DevBuf<double> scratch;
     scratch.alloc(1);
     double* scr = scratch.p;
-    if (a.nmax > a.nlds) {
+    if (a.nmax > a.nlds || tiled) {
         scratch.alloc((size_t)grid * stride);
         scr = scratch.p;
     }
@@ -215,31 +447,26 @@ static void launch_setup(int nt, const SetupArgs& a, hipStream_t s) {
         CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<128>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     }
-    switch (nt) {
-        case 64:
-            hipLaunchKernelGGL(k_fsai_setup<64>, dim3(grid), dim3(64), shm, s, a.nrows, a.order, a.b, a.a_rowptr,
-                               a.a_col, a.a_vals, a.p_rowptr, a.p_col, a.g_vals, a.nlds, scr, stride, a.counter,
-                               a.bad_row);
-            break;
-        case 128:
-            hipLaunchKernelGGL(k_fsai_setup<128>, dim3(grid), dim3(128), shm, s, a.nrows, a.order, a.b, a.a_rowptr,
-                               a.a_col, a.a_vals, a.p_rowptr, a.p_col, a.g_vals, a.nlds, scr, stride, a.counter,
-                               a.bad_row);
-            break;
-        default:
-            hipLaunchKernelGGL(k_fsai_setup<256>, dim3(grid), dim3(256), shm, s, a.nrows, a.order, a.b, a.a_rowptr,
-                               a.a_col, a.a_vals, a.p_rowptr, a.p_col, a.g_vals, a.nlds, scr, stride, a.counter,
-                               a.bad_row);
-            break;
+    auto go = [&](auto kern, int nt) {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), shm, s, a.nrows, a.order, a.b, a.a_rowptr, a.a_col, a.a_vals,
+                           a.p_rowptr, a.p_col, a.g_vals, a.nlds, cfg.ntile, tmaxtiles, scr, stride, a.counter,
+                           a.bad_row);
+    };
+    switch (cfg.nt) {
+        case 64: go(k_fsai_setup<64>, 64); break;
+        case 128: go(k_fsai_setup<128>, 128); break;
+        default: go(k_fsai_setup<256>, 256); break;
     }
     CHF_LAUNCH_CHECK();
     CHF_HIP(hipStreamSynchronize(s));  // scratch is released on return
 }
 
-static int pick_width(const SetupArgs& a, int nmax, hipStream_t s) {
-    if (const char* env = std::getenv("CHF_FSAI_WIDTH")) {
-        int w = std::atoi(env);
-        if (w == 64 || w == 128 || w == 256) return w;
+static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order_host, hipStream_t s) {
+    const int nmax = a.nmax;
+    if (const char* env = std::getenv("CHF_FSAI_CONFIG")) {   // "<width>,<tile threshold>"
+        int w = 0, t = 0;
+        if (std::sscanf(env, "%d,%d", &w, &t) == 2 && (w == 64 || w == 128 || w == 256))
+            return TuneVal{w, t > 0 ? t : NO_TILES};
     }
     TuneKey key{a.b, nmax};
     {
@@ -247,21 +474,32 @@ static int pick_width(const SetupArgs& a, int nmax, hipStream_t s) {
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) return it->second;
     }
-    int best = 64;
+    std::vector<TuneVal> cands = {{64, NO_TILES}, {128, NO_TILES}, {256, NO_TILES}};
+    if (a.b <= 16 && nmax > 48) {
+        cands.push_back({256, 48});
+        if (nmax > 96) cands.push_back({256, 96});
+        if (nmax > 160) cands.push_back({256, 160});
+    }
+    TuneVal best = nmax > 64 ? TuneVal{128, NO_TILES} : TuneVal{64, NO_TILES};
     if (a.nrows >= 4096) {
-        // time a sample: the first rows of the (size-sorted) order
+        // an evenly strided sample of the size-sorted order keeps the size mix
+        const int64_t ns = 8192;
+        std::vector<int64_t> smp_order(std::min<int64_t>(ns, a.nrows));
+        for (size_t i = 0; i < smp_order.size(); ++i)
+            smp_order[i] = order_host[(int64_t)i * a.nrows / (int64_t)smp_order.size()];
+        DevBuf<int64_t> d_smp(smp_order.size());
+        d_smp.upload(smp_order.data(), smp_order.size(), s);
         SetupArgs smp = a;
-        smp.nrows = std::min<int64_t>(a.nrows, 8192);
+        smp.nrows = (int64_t)smp_order.size();
+        smp.order = d_smp.p;
         double best_t = 1e30;
-        for (int w : {64, 128, 256}) {
-            launch_setup(w, smp, s);  // warm-up
+        for (const TuneVal& c : cands) {
+            launch_setup(c, smp, s);  // warm-up
             auto t0 = std::chrono::steady_clock::now();
-            launch_setup(w, smp, s);
+            launch_setup(c, smp, s);
             double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (dt < best_t) { best_t = dt; best = w; }
+            if (dt < best_t) { best_t = dt; best = c; }
         }
-    } else {
-        best = nmax > 64 ? 128 : 64;
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[key] = best;
@@ -365,8 +603,8 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
     if (nb > 0) {
         SetupArgs args{nb, d_order.p, b, A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, d_prow.p, d_pcol.p,
                        G->d_vals.p, std::min(max_lds_n(b), nmax), d_flags.p, d_flags.p + 1, nmax};
-        int width = pick_width(args, nmax, s);
-        launch_setup(width, args, s);
+        TuneVal cfg = pick_config(args, order, s);
+        launch_setup(cfg, args, s);
         int flags[2];
         d_flags.download(flags, 2, s);
         CHF_HIP(hipStreamSynchronize(s));

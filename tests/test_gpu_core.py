@@ -178,3 +178,21 @@ def test_run_twice_bit_identical(chf):
         chf.cheb4_smooth(A, G, 3.0, 4, b_, x, x_is_zero=True, work=w)
         outs.append(host(x))
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("n,dim,b,pw,tmax", [(9, 2, 10, 2, 8), (4, 3, 10, 2, 23), (8, 2, 3, 2, 12), (7, 2, 1, 2, 20)])
+@pytest.mark.parametrize("config", ["256,1", "256,48", "64,0", "128,0"])
+def test_fsai_configs_match_oracle(chf, n, dim, b, pw, tmax, config, monkeypatch):
+    """Every solver configuration (width, tiled-MFMA threshold) gives the
+    oracle's G; '256,1' sends every row through the tiled MFMA path, and the
+    3D t_max = 23 case has local systems up to 240 wide."""
+    from oracle import adaptive
+    p = make_problem(n, dim, b, pw, seed=0)
+    a = from_problem(p)
+    prow, pcol = adaptive.adaptive_pattern(a, tmax)
+    monkeypatch.setenv("CHF_FSAI_CONFIG", config)
+    A = upload(p)
+    G = chf.fsai_setup(A, chf.pattern_from_csr(p.nb, prow, pcol))
+    g = chf.fsai_export(G, len(pcol), b)
+    want = fsai.fsai(a, prow, pcol).vals
+    assert rel_err(g, want) < 1e-12
