@@ -255,26 +255,41 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
             }
         }
         __syncthreads();
-        // (c) trailing tiles A_IJ -= L_Ik L_Jk^T, kt < J <= I < T, on MFMA
+        // (c) trailing tiles A_IJ -= L_Ik L_Jk^T, kt < J <= I < T, on MFMA;
+        // each wavefront keeps four tiles in flight
         const int nt = T - kt - 1;
         const int npairs = nt * (nt + 1) / 2;
-        for (int pidx = wave; pidx < npairs; pidx += 4) {
-            int ii, jj;
-            tri_decode(pidx, ii, jj);
-            double* Ct = tile_at(tiles, kt + 1 + ii, kt + 1 + jj);
-            v4d acc;
+        constexpr int U = 4;
+        for (int base = wave * U; base < npairs; base += 4 * U) {
+            v4d acc[U];
+            double* Ct[U];
+            int ii[U], jj[U];
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) acc[rr] = Ct[(4 * rr + (lane >> 4)) * 16 + (lane & 15)];
-            const double* Li = panel + (ii + 1) * 256;
-            const double* Lj = panel + (jj + 1) * 256;
+            for (int u = 0; u < U; ++u) {
+                const int pidx = min(base + u, npairs - 1);
+                tri_decode(pidx, ii[u], jj[u]);
+                Ct[u] = tile_at(tiles, kt + 1 + ii[u], kt + 1 + jj[u]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double av = -Li[(lane & 15) * 16 + 4 * q + (lane >> 4)];
-                const double bv = Lj[(lane & 15) * 16 + 4 * q + (lane >> 4)];
-                acc = mfma16(av, bv, acc);
+                for (int rr = 0; rr < 4; ++rr) acc[u][rr] = Ct[u][(4 * rr + (lane >> 4)) * 16 + (lane & 15)];
             }
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) Ct[(4 * rr + (lane >> 4)) * 16 + (lane & 15)] = acc[rr];
+            for (int u = 0; u < U; ++u) {
+                const double* Li = panel + (ii[u] + 1) * 256;
+                const double* Lj = panel + (jj[u] + 1) * 256;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double av = -Li[(lane & 15) * 16 + 4 * q + (lane >> 4)];
+                    const double bv = Lj[(lane & 15) * 16 + 4 * q + (lane >> 4)];
+                    acc[u] = mfma16(av, bv, acc[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (base + u < npairs) {
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) Ct[u][(4 * rr + (lane >> 4)) * 16 + (lane & 15)] = acc[u][rr];
+                }
+            }
         }
         __syncthreads();
     }
