@@ -2,7 +2,9 @@
 // SpMV kernels with their fused epilogues (residual, fourth-kind Chebyshev
 // update of Algorithm 3).
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 #include "kernels_common.h"
@@ -121,16 +123,28 @@ void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, boo
 // a time. Workgroups are mapped so that each of the 8 XCDs (which receive
 // workgroups round-robin) works on one contiguous range of slices, keeping the
 // x gathers of neighbouring block rows in that XCD's L2.
-template <int V, typename TA, typename TV>
+// Matrix values are streamed once per product; with NTL they are loaded with
+// the non-temporal hint so that they do not displace the x gathers in L2.
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <int V, typename TA, typename TV, bool NTL = false>
 struct Pair;
-template <typename TA, typename TV>
-struct Pair<1, TA, TV> {
-    __device__ static inline TV dot(const TA* v, const TV* x) { return load_as<TV>(v) * x[0]; }
+template <typename TA, typename TV, bool NTL>
+struct Pair<1, TA, TV, NTL> {
+    __device__ static inline TV dot(const TA* v, const TV* x) {
+        if constexpr (NTL && !std::is_same<TA, bf16_t>::value)
+            return (TV)__builtin_nontemporal_load(v) * x[0];
+        else
+            return load_as<TV>(v) * x[0];
+    }
 };
-template <typename TV>
-struct Pair<2, double, TV> {
+template <typename TV, bool NTL>
+struct Pair<2, double, TV, NTL> {
     __device__ static inline TV dot(const double* v, const TV* x) {
-        const double2 a = *reinterpret_cast<const double2*>(v);
+        d2v a;
+        if constexpr (NTL)
+            a = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(v));
+        else
+            a = *reinterpret_cast<const d2v*>(v);
         if constexpr (sizeof(TV) == 8) {
             const double2 y = *reinterpret_cast<const double2*>(x);
             return a.x * y.x + a.y * y.y;
@@ -139,10 +153,15 @@ struct Pair<2, double, TV> {
         }
     }
 };
-template <typename TV>
-struct Pair<2, float, TV> {
+typedef float f2v __attribute__((ext_vector_type(2)));
+template <typename TV, bool NTL>
+struct Pair<2, float, TV, NTL> {
     __device__ static inline TV dot(const float* v, const TV* x) {
-        const float2 a = *reinterpret_cast<const float2*>(v);
+        f2v a;
+        if constexpr (NTL)
+            a = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(v));
+        else
+            a = *reinterpret_cast<const f2v*>(v);
         if constexpr (sizeof(TV) == 4) {
             const float2 y = *reinterpret_cast<const float2*>(x);
             return a.x * y.x + a.y * y.y;
@@ -151,10 +170,14 @@ struct Pair<2, float, TV> {
         }
     }
 };
-template <typename TV>
-struct Pair<2, bf16_t, TV> {
+template <typename TV, bool NTL>
+struct Pair<2, bf16_t, TV, NTL> {
     __device__ static inline TV dot(const bf16_t* v, const TV* x) {
-        const uint32_t u = *reinterpret_cast<const uint32_t*>(v);
+        uint32_t u;
+        if constexpr (NTL)
+            u = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(v));
+        else
+            u = *reinterpret_cast<const uint32_t*>(v);
         return (TV)bf16_bits_to_f32((uint16_t)(u & 0xffffu)) * x[0] + (TV)bf16_bits_to_f32((uint16_t)(u >> 16)) * x[1];
     }
 };
@@ -165,7 +188,7 @@ __device__ inline int64_t xcd_slice_block(int64_t nwork_blocks) {
     return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <int BT, int V, typename TA, typename TV, int EPI>
+template <int BT, int V, typename TA, typename TV, int EPI, bool NTL>
 __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, int brt,
                                                    const int* __restrict__ soff, const int* __restrict__ cols,
                                                    const TA* __restrict__ vals, const TV* __restrict__ x,
@@ -192,7 +215,7 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, 
         for (int j = j0; j < j1; ++j) {
             const TV* xc = x + (int64_t)(*cp) * BT;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) acc += Pair<V, TA, TV>::dot(v + q * L * V, xc + q * V);
+            for (int q = 0; q < NQ; ++q) acc += Pair<V, TA, TV, NTL>::dot(v + q * L * V, xc + q * V);
             v += stride;
             cp += S;
         }
@@ -201,7 +224,7 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, 
             const int col = cols[(int64_t)j * S + lr];
             const TA* v = vals + (int64_t)j * b * L + lane;
             const TV* xc = x + (int64_t)col * b;
-            for (int c = 0; c < b; ++c) acc += load_as<TV>(v + c * L) * xc[c];
+            for (int c = 0; c < b; ++c) acc += Pair<1, TA, TV, NTL>::dot(v + c * L, xc + c);
         }
     }
     const int64_t o = row * b + r;
@@ -233,12 +256,29 @@ static void launch_spmv_t(const Sell& A, const void* x, void* y, const void* bv,
                            (const TA*)A.vals.p, (const TV*)x, (TV*)y, (const TV*)bv, (TV*)p, (TV*)xo, (TV)alpha,
                            (TV)beta);
     };
-    switch (epi) {
-        case EPI_AX: args(k_sell_spmv<BT, V, TA, TV, EPI_AX>); break;
-        case EPI_RES: args(k_sell_spmv<BT, V, TA, TV, EPI_RES>); break;
-        case EPI_CHEB_FIRST0: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST0>); break;
-        case EPI_CHEB_FIRST: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST>); break;
-        default: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB>); break;
+    // non-temporal matrix loads are the default (measured at 512^2, b = 10:
+    // residual SpMV 78 % instead of 71 % of HBM peak); CHF_SPMV_NONTEMPORAL=0
+    // turns them off
+    static const bool ntl = [] {
+        const char* e = std::getenv("CHF_SPMV_NONTEMPORAL");
+        return !(e && e[0] == '0');
+    }();
+    if (ntl) {
+        switch (epi) {
+            case EPI_AX: args(k_sell_spmv<BT, V, TA, TV, EPI_AX, true>); break;
+            case EPI_RES: args(k_sell_spmv<BT, V, TA, TV, EPI_RES, true>); break;
+            case EPI_CHEB_FIRST0: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST0, true>); break;
+            case EPI_CHEB_FIRST: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST, true>); break;
+            default: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB, true>); break;
+        }
+    } else {
+        switch (epi) {
+            case EPI_AX: args(k_sell_spmv<BT, V, TA, TV, EPI_AX, false>); break;
+            case EPI_RES: args(k_sell_spmv<BT, V, TA, TV, EPI_RES, false>); break;
+            case EPI_CHEB_FIRST0: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST0, false>); break;
+            case EPI_CHEB_FIRST: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB_FIRST, false>); break;
+            default: args(k_sell_spmv<BT, V, TA, TV, EPI_CHEB, false>); break;
+        }
     }
     CHF_LAUNCH_CHECK();
 }
