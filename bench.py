@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-setup3d", action="store_true")
     ap.add_argument("--setup3d-grid", type=int, default=32, help="3D patch grid of the batched set-up leg")
     ap.add_argument("--setup3d-tmax", type=int, default=23)
+    ap.add_argument("--only-setup3d", action="store_true",
+                    help="run only the batched 3D set-up leg (for hardware-counter passes)")
     ap.add_argument("--train-seeds", type=int, default=32, help="training seeds 1..S")
     ap.add_argument("--test-seeds", type=int, default=2, help="test seeds 100..100+T-1 (up to 8)")
     ap.add_argument("--cpu-grid", type=int, default=32, help="patches per side of the oracle's timing sample")
@@ -235,6 +237,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.only_setup3d:
+        print(json.dumps({"setup3d": setup3d_leg(args, chf, torch)}), flush=True)
+        return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

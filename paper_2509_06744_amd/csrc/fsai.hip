@@ -130,16 +130,25 @@ __device__ void fsai_row(int64_t k, int b, const int* __restrict__ a_rowptr, con
 // ------------------------------------------------- tiled MFMA local solver --
 // For larger local systems (n > ntile, b <= 16) the factorisation works on
 // 16 x 16 tiles of the lower triangle, held in the workgroup's global scratch
-// slot (L2/MALL resident): per tile column, one wavefront factors the
-// diagonal tile in registers, one thread per (tile, row) solves the panel, and
-// the four wavefronts update the trailing tiles with FP64 MFMA
-// (v_mfma_f64_16x16x4: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]
-// and receives D[4 r + l / 16][l % 16] in register r). The b right-hand sides
-// of L^T Z = E are solved by tile rows with MFMA accumulations. Padding rows
-// of the last tile are identity rows.
+// slot (L2/MALL resident). Per tile column, one wavefront factors the diagonal
+// tile and inverts its factor in registers (the only sequential step); the
+// panel L_ik = A_ik L_kk^{-T} and the trailing update A_IJ -= L_Ik L_Jk^T are
+// FP64 MFMA products over the four wavefronts (v_mfma_f64_16x16x4: lane l
+// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
+// D[4 r + l / 16][l % 16] in register r). The b right-hand sides of
+// L^T Z = E are solved by tile rows, Z_I = L_II^{-T}(E_I - sum L_JI^T Z_J),
+// also on MFMA. Padding rows of the last tile are identity rows.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ inline v4d mfma16(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+
+// Broadcast of lane l's value to the wavefront through scalar registers
+// (v_readlane), cheaper than an LDS permute when l is a compile-time constant.
+__device__ inline double lane_bcast(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
 
 __device__ inline double* tile_at(double* base, int I, int J) { return base + ((int64_t)I * (I + 1) / 2 + J) * 256; }
 
@@ -154,7 +163,8 @@ __device__ inline void tri_decode(int t, int& I, int& J) {
 __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                const double* __restrict__ a_vals, const int64_t* __restrict__ p_rowptr,
                                const int* __restrict__ p_col, double* __restrict__ g_vals, double* tiles,
-                               double* panel, double* Zl, double* part, int* idx, int* sh_flag, int* bad_row) {
+                               double* panel, double* Zl, double* invs, double* part, int* idx, int* sh_flag,
+                               int* bad_row) {
     constexpr int NT = 256;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t p0 = p_rowptr[k];
@@ -200,7 +210,9 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
     if (tid == 0) sh_flag[0] = 1;
     __syncthreads();
     for (int kt = 0; kt < T; ++kt) {
-        // (a) diagonal tile, one wavefront, rows in registers
+        // (a) diagonal tile, one wavefront, rows in registers: L_kk = chol(A_kk)
+        // and its inverse X = L_kk^{-1} (row r of X is finished once the rows
+        // above it are, so rows are completed in order and broadcast by shuffles)
         if (wave == 0) {
             double* Dt = tile_at(tiles, kt, kt);
             const int r = lane & 15;
@@ -210,48 +222,60 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
             bool ok = true;
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const double dq = __shfl(row[q], q, 64);
+                const double dq = lane_bcast(row[q], q);
                 ok = ok && (dq > 0.0) && isfinite(dq);
                 const double lqq = sqrt(fmax(dq, 1e-300));
                 const double lrq = (r > q) ? row[q] / lqq : (r == q ? lqq : 0.0);
                 row[q] = lrq;
 #pragma unroll
                 for (int j = q + 1; j < 16; ++j) {
-                    const double ljq = __shfl(lrq, j, 64);
+                    const double ljq = lane_bcast(lrq, j);
                     if (j <= r) row[j] -= lrq * ljq;
                 }
             }
+            double acc[16], xr[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) { acc[c] = 0.0; xr[c] = 0.0; }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const double dinv = 1.0 / lane_bcast(row[q], q);       // 1 / L[q][q]
+#pragma unroll
+                for (int c = 0; c <= q; ++c) {
+                    const double xq = ((q == c ? 1.0 : 0.0) - acc[c]) * dinv;   // X[q][c] on lane q
+                    const double v = lane_bcast(xq, q);
+                    if (r == q) xr[c] = v;
+                    if (r > q) acc[c] += row[q] * v;
+                }
+            }
             if (lane < 16) {
+                double* inv = invs + kt * 256;
 #pragma unroll
                 for (int c = 0; c < 16; ++c) {
-                    const double v = c <= r ? row[c] : 0.0;
+                    const double v = c <= r ? xr[c] : 0.0;
                     panel[r * 16 + c] = v;
-                    Dt[r * 16 + c] = v;
+                    inv[r * 16 + c] = v;
                 }
             }
             if (lane == 0 && !ok) sh_flag[0] = 0;
         }
         __syncthreads();
         if (!sh_flag[0]) break;
-        // (b) panel: L_ik = A_ik L_kk^{-T}, one thread per (tile, row)
-        for (int w = tid; w < (T - kt - 1) * 16; w += NT) {
-            const int ti = kt + 1 + w / 16, r = w & 15;
+        // (b) panel: L_ik = A_ik L_kk^{-T} = A_ik X^T on MFMA, one tile per wavefront
+        for (int ti = kt + 1 + wave; ti < T; ti += 4) {
             double* Tt = tile_at(tiles, ti, kt);
-            double x[16];
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < 16; ++c) x[c] = Tt[r * 16 + c];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                double sacc = x[c];
-#pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    if (q < c) sacc -= x[q] * panel[c * 16 + q];
-                x[c] = sacc / panel[c * 16 + c];
+            for (int q = 0; q < 4; ++q) {
+                const double av = Tt[(lane & 15) * 16 + 4 * q + (lane >> 4)];          // A_ik[row][4q+k]
+                const double bv = panel[(lane & 15) * 16 + 4 * q + (lane >> 4)];       // X^T[4q+k][col] = X[col][4q+k]
+                acc = mfma16(av, bv, acc);
             }
+            double* pt = panel + (ti - kt) * 256;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) {
-                Tt[r * 16 + c] = x[c];
-                panel[(ti - kt) * 256 + r * 16 + c] = x[c];
+            for (int rr = 0; rr < 4; ++rr) {
+                const int o = (4 * rr + (lane >> 4)) * 16 + (lane & 15);
+                Tt[o] = acc[rr];
+                pt[o] = acc[rr];
             }
         }
         __syncthreads();
@@ -299,12 +323,8 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
         __syncthreads();
         return;
     }
-    // L^T Z = E (Z: 16T x 16, columns c < b carry the last b unit vectors)
-    for (int e = tid; e < T * 256; e += NT) {
-        const int i = e >> 4, c = e & 15;
-        Zl[e] = (c < b && i == n - b + c) ? 1.0 : 0.0;
-    }
-    __syncthreads();
+    // L^T Z = E (Z: 16T x 16, columns c < b carry the last b unit vectors),
+    // by tile rows: Z_I = X_II^T (E_I - sum_{J > I} L_JI^T Z_J) on MFMA
     for (int I = T - 1; I >= 0; --I) {
         v4d acc = {0.0, 0.0, 0.0, 0.0};
         for (int J = I + 1 + wave; J < T; J += 4) {
@@ -319,25 +339,24 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) part[wave * 256 + (4 * rr + (lane >> 4)) * 16 + (lane & 15)] = acc[rr];
         __syncthreads();
-        if (tid < 16) {
-            const int c = tid;
-            const double* LII = tile_at(tiles, I, I);
-            double z[16];
+        // R = E_I - S, stored row-major in part[4 * 256 ...]
+        for (int e = tid; e < 256; e += NT) {
+            const int r = e >> 4, c = e & 15;
+            const double ev = (c < b && 16 * I + r == n - b + c) ? 1.0 : 0.0;
+            part[1024 + e] = ev - (part[e] + part[256 + e] + part[512 + e] + part[768 + e]);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const double* XII = invs + I * 256;
+            v4d z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int o = r * 16 + c;
-                z[r] = Zl[(16 * I + r) * 16 + c] - (part[o] + part[256 + o] + part[512 + o] + part[768 + o]);
+            for (int q = 0; q < 4; ++q) {
+                const double av = XII[(4 * q + (lane >> 4)) * 16 + (lane & 15)];          // X^T[row][4q+k]
+                const double bv = part[1024 + (4 * q + (lane >> 4)) * 16 + (lane & 15)];  // R[4q+k][col]
+                z = mfma16(av, bv, z);
             }
 #pragma unroll
-            for (int r = 15; r >= 0; --r) {
-                double sacc = z[r];
-#pragma unroll
-                for (int q = 0; q < 16; ++q)
-                    if (q > r) sacc -= LII[q * 16 + r] * z[q];
-                z[r] = sacc / LII[r * 16 + r];
-            }
-#pragma unroll
-            for (int r = 0; r < 16; ++r) Zl[(16 * I + r) * 16 + c] = z[r];
+            for (int rr = 0; rr < 4; ++rr) Zl[(16 * I + 4 * rr + (lane >> 4)) * 16 + (lane & 15)] = z[rr];
         }
         __syncthreads();
     }
@@ -383,10 +402,11 @@ __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t*
         if constexpr (NT == 256) {
             if (n > ntile && b <= 16) {
                 double* panel = lds;
-                double* Zl = panel + (int64_t)tmaxtiles * 256;
-                double* part = Zl + (int64_t)tmaxtiles * 256;
-                fsai_row_tiled(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, gK, panel, Zl, part, idx,
-                               sh_flag, bad_row);
+                double* part = panel + (int64_t)tmaxtiles * 256;
+                double* Zl = gK + (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256;   // global, after the tiles
+                double* invs = Zl + (int64_t)tmaxtiles * 256;                       // inverses of diagonal tiles
+                fsai_row_tiled(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, gK, panel, Zl, invs, part,
+                               idx, sh_flag, bad_row);
                 continue;
             }
         }
@@ -439,20 +459,24 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s) {
     const int cus = device_cu_count();
     const bool tiled = cfg.nt == 256 && a.b <= 16 && a.nmax > cfg.ntile;
     const int tmaxtiles = (a.nmax + 15) / 16;
-    size_t shm = lds_bytes(a.nlds, a.b);
-    if (tiled) shm = std::max(shm, ((size_t)tmaxtiles * 256 * 2 + 4 * 256) * sizeof(double));
+    // rows above the tile threshold never use the scalar LDS solver, so its
+    // buffer only needs the threshold's size (more workgroups per CU)
+    const int nlds = tiled ? std::min(a.nlds, cfg.ntile) : a.nlds;
+    size_t shm = lds_bytes(nlds, a.b);
+    if (tiled) shm = std::max(shm, ((size_t)tmaxtiles * 256 + 5 * 256) * sizeof(double));
     int dev = 0, lim = 0;
     CHF_HIP(hipGetDevice(&dev));
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / (shm + 4096 + 64)));
     int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(1, a.nrows));
     int64_t stride = (int64_t)FSAI_MAXN * (FSAI_MAXN + 1) / 2 + (int64_t)FSAI_MAXN * a.b;
-    if (tiled) stride = std::max<int64_t>(stride, (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256);
+    if (tiled)
+        stride = std::max<int64_t>(stride, (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256 + 2 * (int64_t)tmaxtiles * 256);
     // global scratch only when some row exceeds the LDS limit or is tiled
     DevBuf<double> scratch;
     scratch.alloc(1);
     double* scr = scratch.p;
-    if (a.nmax > a.nlds || tiled) {
+    if (a.nmax > nlds || tiled) {
         scratch.alloc((size_t)grid * stride);
         scr = scratch.p;
     }
@@ -464,7 +488,7 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s) {
     }
     auto go = [&](auto kern, int nt) {
         hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), shm, s, a.nrows, a.order, a.b, a.a_rowptr, a.a_col, a.a_vals,
-                           a.p_rowptr, a.p_col, a.g_vals, a.nlds, cfg.ntile, tmaxtiles, scr, stride, a.counter,
+                           a.p_rowptr, a.p_col, a.g_vals, nlds, cfg.ntile, tmaxtiles, scr, stride, a.counter,
                            a.bad_row);
     };
     switch (cfg.nt) {
@@ -490,8 +514,9 @@ static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order
         if (it != g_tuned.end()) return it->second;
     }
     std::vector<TuneVal> cands = {{64, NO_TILES}, {128, NO_TILES}, {256, NO_TILES}};
-    if (a.b <= 16 && nmax > 48) {
-        cands.push_back({256, 48});
+    if (a.b <= 16 && nmax > 32) {
+        cands.push_back({256, 32});
+        if (nmax > 48) cands.push_back({256, 48});
         if (nmax > 96) cands.push_back({256, 96});
         if (nmax > 160) cands.push_back({256, 160});
     }
