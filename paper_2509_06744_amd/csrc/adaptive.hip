@@ -1,20 +1,26 @@
 // Adaptive block-FSAI pattern (Algorithm 1 with the ratio of Lemma 2.4) on the
 // GPU. Block rows evolve independently (row k of F depends only on A and
-// P_k), so one workgroup owns one row for all t_max steps.
+// P_k), so one single-wavefront workgroup owns one row for all t_max steps.
 //
-// Per row, with P~ the off-diagonal part of P_k kept in insertion order:
-//   L  = chol(A[P~, P~])                (extended by one block row per step)
-//   Y_k = L^{-1} A[P~, k],  H_kk = A_kk - Y_k^T Y_k = (F A F^T)_kk
-// and for each candidate c (c < k, c not in P_k, (FA)_kc structurally
-// nonzero, i.e. c in the pattern of some row A_j with j in P_k):
-//   Y_c = L^{-1} A[P~, c],  H_kc = A_kc - Y_k^T Y_c,  W_c = A_cc - Y_c^T Y_c,
+// For a row k with current pattern P_k = P~ + {k} and a candidate c (c < k,
+// c not in P_k, (FA)_kc structurally nonzero, i.e. c in the pattern of some
+// row A_j with j in P_k):
+//   H_kk = A_kk - A[k,P~] A[P~,P~]^{-1} A[P~,k]   (= (F A F^T)_kk),
+//   H_kc = A_kc - A[k,P~] A[P~,P~]^{-1} A[P~,c]   (= (F A)_kc),
+//   W_c  = A_cc - A[c,P~] A[P~,P~]^{-1} A[P~,c],
 //   rho_c = det(W_c - H_kc^T H_kk^{-1} H_kc) / det(W_c) = det(I - X X^T),
 //   X = L_W^{-1} H_kc^T L_H^{-T}   (W_c = L_W L_W^T, H_kk = L_H L_H^T),
 //   g_c = -log rho_c, evaluated by a Cholesky of I - X X^T with log1p pivots.
 // The best candidate c* (largest g; ties within a relative 1e-9 of the best go
-// to the smallest block index) enters when g* > -log(tau) + 1e-12. Adding c*
-// appends [Y_c*^T, L_W] to L, L_W^{-1} H_kc*^T to Y_k, and updates H_kk.
+// to the smallest block index) enters when g* > -log(tau) + 1e-12.
+//
+// Two evaluations live here. ad_batch forms H_kc and W_c from scratch for a
+// batch of candidates (Y_c = L^{-1} A[P~,c] with L = chol(A[P~,P~])); the
+// learned-pattern features use it with P~ empty. The pattern kernel
+// (ai_row) keeps A[P~,P~]^{-1} and every candidate's H_kc, W_c across the
+// steps and updates them when a block enters (described at ai_row).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 
@@ -273,163 +279,632 @@ __device__ void ad_batch(int k, int b, int NB, int m, int M, const int* plist, c
     __syncthreads();
 }
 
-template <int MAXB, int NT>
-__device__ void ad_row(int k, int b, int tmax, double thresh, const int* __restrict__ a_rowptr,
-                       const int* __restrict__ a_col, const double* __restrict__ a_vals, int* __restrict__ out_cols,
-                       int* __restrict__ out_cnt, double* base, double* __restrict__ Ybuf, int* plist, int* cand,
-                       double* gain, double* part, int* sh, int* err) {
-    const int lane = threadIdx.x;
-    const int NB = (NT / 64) * (64 / b);
-    const int Mmax = (tmax - 1) * b;   // L, Y_k and Y_c never grow past t_max - 1 blocks
-    const int bb = b * b;
-    AdRegion R = ad_region(base, Mmax, b, NB);
-    // sh[0] = ncand, sh[1] = m, sh[2] = c*, sh[3] = flag, sh[4] = continue
-    // init: H_kk = A_kk, candidates = pattern of A_k left of the diagonal
-    const int ekk = find_block(a_rowptr, a_col, k, k);
-    for (int e = lane; e < bb; e += NT) R.Hkk[e] = ekk >= 0 ? a_vals[(int64_t)ekk * bb + e] : 0.0;
-    if (lane == 0) {
-        int nc = 0;
-        for (int e = a_rowptr[k]; e < a_rowptr[k + 1]; ++e) {
-            int c = a_col[e];
-            if (c < k && nc < AD_MAXC) cand[nc++] = c;
+// ------------------------------------------------------ Algorithm 1 rows --
+// Incremental form. State of a row, with P~ in insertion order and
+// M = b |P~|:
+//   Kinv = A[P~,P~]^{-1}                       (packed lower, M x M)
+//   H_kk = A_kk - A[k,P~] Kinv A[P~,k],  L_H = chol(H_kk)
+//   per candidate c:  W_c  = A_cc - A[c,P~] Kinv A[P~,c]
+//                     H_kc = A_kc - A[k,P~] Kinv A[P~,c]
+//                     the (position in P~, block index of A_jc) of every
+//                     j in P~ with A_jc structurally nonzero.
+// Adding c* (S = W_c* = L_S L_S^T is the Schur complement of A[P~,P~] in
+// A[P~ + c*, P~ + c*]) changes them by the bordering identities
+//   V = Kinv A[P~,c*],  U = L_S^{-1} H_kc*^T,  H_kk -= U^T U,
+//   E_c = A_c*c - V^T A[P~,c],  e_c = L_S^{-1} E_c,
+//   W_c -= e_c^T e_c,  H_kc -= U^T e_c,
+//   Kinv <- [[Kinv + Vt Vt^T, -Vt L_S^{-1}], [-L_S^{-T} Vt^T, L_S^{-T} L_S^{-1}]],
+//   Vt = V L_S^{-T},
+// so a step costs O(b^3) per candidate (A[P~,c] has few nonzero blocks)
+// plus O(M^2 b) once, instead of a triangular solve with L per candidate.
+// Candidates that c* brings in start from W_c = A_cc, H_kc = A_kc (their
+// A[P~,c] was empty) and receive the same update.
+
+__host__ __device__ inline int64_t ai_tri(int64_t i) { return i * (i + 1) / 2; }
+
+__device__ inline int64_t kidx(int i, int j) { return i >= j ? ai_tri(i) + j : ai_tri(j) + i; }
+
+struct AiState {
+    double* kinv;   // atri(Mmax)
+    double* V;      // Mmax x b
+    double* Vt;     // Mmax x b
+    double* W;      // cap x b x b
+    double* H;      // cap x b x b
+    double* gain;   // cap
+    int* cand;      // cap
+    int* nzn;       // cap
+    int* nzp;       // cap x AD_MAXP
+    int* nze;       // cap x AD_MAXP
+};
+
+__host__ __device__ inline int64_t ai_global_doubles(int Mmax, int b, int cap, bool kinv_g, bool v_g) {
+    const int64_t ints = (int64_t)cap * (2 + 2 * AD_MAXP);
+    return (kinv_g ? ai_tri(Mmax) : 0) + (v_g ? 2 * (int64_t)Mmax * b : 0) + 2 * (int64_t)cap * b * b + cap +
+           (ints + 1) / 2;
+}
+
+__host__ __device__ inline int64_t ai_lds_doubles(int Mmax, int b, bool kinv_l, bool v_l) {
+    const int NB = 64 / b;
+    return 5 * (int64_t)b * b + (int64_t)NB * (3 * b * b + 2 * b) + (kinv_l ? ai_tri(Mmax) : 0) +
+           (v_l ? 2 * (int64_t)Mmax * b : 0);
+}
+
+// Cholesky of one b x b SPD matrix per group of b lanes; lane r holds row r
+// (w[j] = A[r][j], j <= r) and ends with row r of the factor. One barrier
+// per pivot: the pivot column is published to cb (two alternating buffers of
+// b doubles) and every lane forms its own multipliers. All lanes of the
+// workgroup must call it.
+template <int MAXB>
+__device__ inline void group_chol(double (&w)[MAXB], int b, int r, bool act, double* cb, bool& ok) {
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        if (q < b) {
+            double* c = cb + (q & 1) * b;
+            if (act && r >= q) c[r] = w[q];
+            __syncthreads();
+            if (act && r >= q) {
+                const double d = c[q];
+                ok = ok && d > 0.0 && isfinite(d);
+                const double dd = fmax(d, 1e-300);
+                const double sd = sqrt(dd), inv = 1.0 / dd;
+                const double cr = c[r] * inv;
+                w[q] = r == q ? sd : c[r] / sd;
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j)
+                    if (j > q && j <= r) w[j] -= cr * c[j];
+            }
         }
-        sh[0] = nc;
-        sh[1] = 0;
+    }
+}
+
+// One pass over the candidates in slots [s0, s0 + cnt): apply the pending
+// update of the block added last (when `pending`), then g_c = -log rho_c.
+// Lane (ci, r) works on candidate s0 + ci, row/column r of its blocks.
+template <int MAXB>
+__device__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar, int mold,
+                         const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
+                         const double* __restrict__ a_vals, const AiState& S, const double* V, const double* LSinv,
+                         const double* U, const double* LH, double* gbufs, int* flag) {
+    const int lane = threadIdx.x;
+    const int bb = b * b;
+    const int ci = lane / b, r = lane - ci * b;
+    const bool act = ci < cnt;
+    const int slot = s0 + ci;
+    double* cb = gbufs + (act ? ci : 0) * (3 * bb + 2 * b);
+    double* B1 = cb + 2 * b;   // e_c, then Z
+    double* BL = B1 + bb;      // L_W
+    double* BX = BL + bb;      // X
+    double w[MAXB], h[MAXB];
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i)
+            if (i < b) {
+                w[i] = S.W[(int64_t)slot * bb + i * b + r];
+                h[i] = S.H[(int64_t)slot * bb + i * b + r];
+            }
+    }
+    if (pending) {
+        double et[MAXB];
+        int ecs = -1, nn = 0;
+        if (act) {
+            const int c = S.cand[slot];
+            ecs = find_block(a_rowptr, a_col, cstar, c);
+            double e[MAXB];
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i)
+                if (i < b) e[i] = ecs >= 0 ? a_vals[(int64_t)ecs * bb + i * b + r] : 0.0;
+            nn = S.nzn[slot];
+            #pragma unroll 1
+            for (int t = 0; t < nn; ++t) {
+                const int pos = S.nzp[(int64_t)slot * AD_MAXP + t];
+                const int ea = S.nze[(int64_t)slot * AD_MAXP + t];
+                #pragma unroll 1
+                for (int q = 0; q < b; ++q) {
+                    const double aq = a_vals[(int64_t)ea * bb + q * b + r];
+                    const double* vr = V + (int64_t)(pos * b + q) * b;
+#pragma unroll
+                    for (int i = 0; i < MAXB; ++i)
+                        if (i < b) e[i] -= vr[i] * aq;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i)
+                if (i < b) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int q = 0; q < MAXB; ++q)
+                        if (q <= i) s += LSinv[i * b + q] * e[q];
+                    et[i] = s;
+                    B1[i * b + r] = s;
+                }
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i)
+                if (i < b) {
+                    double sw = 0.0, sh = 0.0;
+#pragma unroll
+                    for (int q = 0; q < MAXB; ++q)
+                        if (q < b) {
+                            sw += B1[q * b + i] * et[q];
+                            sh += U[q * b + i] * et[q];
+                        }
+                    w[i] -= sw;
+                    h[i] -= sh;
+                    S.W[(int64_t)slot * bb + i * b + r] = w[i];
+                    S.H[(int64_t)slot * bb + i * b + r] = h[i];
+                }
+            if (r == 0 && ecs >= 0) {
+                S.nzp[(int64_t)slot * AD_MAXP + nn] = mold;
+                S.nze[(int64_t)slot * AD_MAXP + nn] = ecs;
+                S.nzn[slot] = nn + 1;
+            }
+        }
+    }
+    // L_W = chol(W_c)
+    bool ok = true;
+    group_chol<MAXB>(w, b, r, act, cb, ok);
+    if (act) {
+        // rows of L_W; Z = L_H^{-1} H_kc, column r
+        double z[MAXB];
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i)
+            if (i < b) {
+                BL[r * b + i] = i <= r ? w[i] : 0.0;
+                double s = h[i];
+#pragma unroll
+                for (int q = 0; q < MAXB; ++q)
+                    if (q < i) s -= LH[i * b + q] * z[q];
+                z[i] = s / LH[i * b + i];
+                B1[i * b + r] = z[i];
+            }
     }
     __syncthreads();
-    bool ok = small_chol(R.Hkk, R.LH, b, lane, sh + 3);
-    if (!ok) {
+    if (act) {
+        // X = L_W^{-1} Z^T, column r (X = L_W^{-1} H_kc^T L_H^{-T})
+        double x[MAXB];
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i)
+            if (i < b) {
+                double s = B1[r * b + i];
+#pragma unroll
+                for (int q = 0; q < MAXB; ++q)
+                    if (q < i) s -= BL[i * b + q] * x[q];
+                x[i] = s / BL[i * b + i];
+                BX[i * b + r] = x[i];
+            }
+    }
+    __syncthreads();
+    // row r of N = X X^T (lower part)
+    double n[MAXB];
+    if (act) {
+        double xr[MAXB];
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q)
+            if (q < b) xr[q] = BX[r * b + q];
+#pragma unroll
+        for (int s = 0; s < MAXB; ++s)
+            if (s < b && s <= r) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < MAXB; ++q)
+                    if (q < b) acc += xr[q] * BX[s * b + q];
+                n[s] = acc;
+            }
+    }
+    // -log det(I - N): Cholesky of I - N carried on N (the pivot of step q is
+    // 1 - s_q with s_q the current N_qq, logged as log1p(-s_q)); every lane
+    // sees every pivot and accumulates the sum itself.
+    double lg = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAXB; ++q) {
+        if (q < b) {
+            double* c = cb + (q & 1) * b;
+            if (act && r >= q) c[r] = n[q];
+            __syncthreads();
+            if (act) {
+                const double sq = c[q];
+                ok = ok && sq < 1.0;
+                lg += log1p(-sq);
+                if (r > q) {
+                    const double cr = c[r] / fmax(1.0 - sq, 1e-300);
+#pragma unroll
+                    for (int j = 0; j < MAXB; ++j)
+                        if (j > q && j <= r) n[j] += cr * c[j];
+                }
+            }
+        }
+    }
+    if (act && r == 0) S.gain[slot] = -lg;
+    if (act && !ok) *flag = 0;
+}
+
+template <int MAXB>
+__device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int* __restrict__ a_rowptr,
+                       const int* __restrict__ a_col, const double* __restrict__ a_vals, int* __restrict__ out_cols,
+                       int* __restrict__ out_cnt, const AiState& S, double* sm, double* gbufs, int* plist, int* sh,
+                       int* err) {
+    const int lane = threadIdx.x;
+    const int bb = b * b;
+    const int NB = 64 / b;
+    double* Hkk = sm;
+    double* LH = Hkk + bb;
+    double* LS = LH + bb;
+    double* LSinv = LS + bb;
+    double* U = LSinv + bb;
+    const bool g0 = lane < b;   // group 0 does the single b x b factorisations
+    const int r = lane;
+    // H_kk = A_kk, L_H; candidates: A_kc != 0, c < k, with W_c = A_cc, H_kc = A_kc
+    const int ekk = find_block(a_rowptr, a_col, k, k);
+    #pragma unroll 1
+    for (int e = lane; e < bb; e += 64) Hkk[e] = ekk >= 0 ? a_vals[(int64_t)ekk * bb + e] : 0.0;
+    int ncand = 0;
+    {
+        const int r0 = a_rowptr[k], r1 = a_rowptr[k + 1];
+        #pragma unroll 1
+        for (int base = r0; base < r1; base += 64) {
+            const int e = base + lane;
+            const bool f = e < r1 && a_col[e] < k;
+            const unsigned long long m = __ballot(f);
+            if (f) {
+                const int slot = ncand + __popcll(m & ((1ull << lane) - 1));
+                if (slot < cap) {
+                    S.cand[slot] = a_col[e];
+                    S.nzn[slot] = 0;
+                }
+            }
+            ncand += __popcll(m);
+        }
+    }
+    if (lane == 0) sh[3] = 1;
+    __syncthreads();
+    if (ncand > cap) {
+        if (lane == 0) atomicMin(err, k);
+        ncand = 0;
+    }
+    #pragma unroll 1
+    for (int t = lane; t < ncand * bb; t += 64) {
+        const int slot = t / bb, e = t - slot * bb;
+        const int c = S.cand[slot];
+        const int ecc = find_block(a_rowptr, a_col, c, c);
+        const int ekc = find_block(a_rowptr, a_col, k, c);
+        S.W[(int64_t)slot * bb + e] = ecc >= 0 ? a_vals[(int64_t)ecc * bb + e] : 0.0;
+        S.H[(int64_t)slot * bb + e] = ekc >= 0 ? a_vals[(int64_t)ekc * bb + e] : 0.0;
+    }
+    bool ok = true;
+    {
+        double w[MAXB];
+#pragma unroll
+        for (int j = 0; j < MAXB; ++j)
+            if (j < b) w[j] = g0 ? Hkk[r * b + j] : 0.0;
+        group_chol<MAXB>(w, b, r, g0, gbufs, ok);
+        if (g0)
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j < b) LH[r * b + j] = j <= r ? w[j] : 0.0;
+        if (g0 && !ok) sh[3] = 0;
+    }
+    __syncthreads();
+    if (!sh[3]) {
         if (lane == 0) atomicMin(err, k);
     }
-    for (int t = 0; t < tmax && ok; ++t) {
-        const int nc = sh[0];
-        const int m = sh[1];
-        const int M = m * b;
-        if (nc == 0) break;
-        for (int s0 = 0; s0 < nc; s0 += NB) {
-            ad_batch<MAXB, NT>(k, b, NB, m, M, plist, cand, s0, min(NB, nc - s0), a_rowptr, a_col, a_vals, R, Ybuf,
-                               gain, part, sh + 3, err);
-            if (!sh[3]) { ok = false; break; }
-        }
-        if (!ok) break;
-        // selection: best gain, ties to the smallest block index
-        if (lane == 0) {
-            double gmax = -1e300;
-            for (int i = 0; i < nc; ++i) gmax = fmax(gmax, gain[i]);
-            const double lim = gmax - AD_TIE_REL * fabs(gmax);
-            int best = -1;
-            for (int i = 0; i < nc; ++i)
-                if (gain[i] >= lim && (best < 0 || cand[i] < cand[best])) best = i;
-            sh[2] = best;
-            sh[4] = (gmax > thresh) ? 1 : 0;
-        }
+    int m = 0;
+    bool pending = false;
+    int cstar = -1;
+    #pragma unroll 1
+    for (int step = 0; step < tmax && sh[3]; ++step) {
+        if (ncand == 0) break;
+        #pragma unroll 1
+        for (int s0 = 0; s0 < ncand; s0 += NB)
+            ai_batch<MAXB>(k, b, s0, min(NB, ncand - s0), pending, cstar, m - 1, a_rowptr, a_col, a_vals, S, S.V,
+                           LSinv, U, LH, gbufs, sh + 3);
         __syncthreads();
-        if (!sh[4]) break;
-        const int bi = sh[2];
-        if (t == tmax - 1) {
-            // last step: the pattern grows, nothing else is needed afterwards
-            if (lane == 0) {
-                plist[m] = cand[bi];
-                sh[1] = m + 1;
-            }
-            __syncthreads();
-            break;
-        }
-        // recompute Y, L_W and U for c* alone (group 0)
-        ad_batch<MAXB, NT>(k, b, NB, m, M, plist, cand, bi, 1, a_rowptr, a_col, a_vals, R, Ybuf, nullptr, part,
-                           sh + 3, err);
-        if (!sh[3]) { ok = false; break; }
-        // extend L by [Y_c*^T, L_W], Y_k by U, H_kk -= U^T U
-        for (int t2 = lane; t2 < b * (M + b); t2 += NT) {
-            int r = t2 / (M + b), i = t2 - r * (M + b);
-            double v;
-            if (i < M) v = Ybuf[(int64_t)i * NT + r];
-            else v = (i - M <= r) ? R.W[r * b + (i - M)] : 0.0;
-            if (i <= M + r) R.L[atri(M + r) + i] = v;
-        }
-        for (int e = lane; e < bb; e += NT) R.Yk[(int64_t)M * b + e] = R.U[e];
-        __syncthreads();
-        for (int e = lane; e < bb; e += NT) {
-            int r = e / b, s = e - r * b;
-            double acc = 0.0;
-            for (int q = 0; q < b; ++q) acc += R.U[q * b + r] * R.U[q * b + s];
-            R.Hkk[e] -= acc;
-        }
-        __syncthreads();
-        ok = small_chol(R.Hkk, R.LH, b, lane, sh + 3);
-        if (!ok) {
+        if (!sh[3]) {
             if (lane == 0) atomicMin(err, k);
             break;
         }
-        // update the pattern and the candidate list
-        if (lane == 0) {
-            const int cstar = cand[bi];
-            plist[m] = cstar;
-            sh[1] = m + 1;
-            int ncand = nc;
-            for (int i = bi; i + 1 < ncand; ++i) cand[i] = cand[i + 1];
-            --ncand;
-            for (int e = a_rowptr[cstar]; e < a_rowptr[cstar + 1]; ++e) {
-                const int c = a_col[e];
-                if (c >= k) break;
-                bool inp = false;
-                for (int q = 0; q <= m; ++q) inp |= plist[q] == c;
-                if (inp) continue;
-                int pos = 0;
-                while (pos < ncand && cand[pos] < c) ++pos;
-                if (pos < ncand && cand[pos] == c) continue;
-                if (ncand >= AD_MAXC) { atomicMin(err, k); break; }
-                for (int i = ncand; i > pos; --i) cand[i] = cand[i - 1];
-                cand[pos] = c;
-                ++ncand;
-            }
-            sh[0] = ncand;
+        // selection: largest gain; ties within a relative AD_TIE_REL of it go
+        // to the smallest block index
+        double gm = -1e300;
+        #pragma unroll 1
+        for (int i = lane; i < ncand; i += 64) gm = fmax(gm, S.gain[i]);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) gm = fmax(gm, __shfl_xor(gm, o, 64));
+        const double lim = gm - AD_TIE_REL * fabs(gm);
+        long long best = LLONG_MAX;
+        #pragma unroll 1
+        for (int i = lane; i < ncand; i += 64)
+            if (S.gain[i] >= lim) best = min(best, ((long long)S.cand[i] << 32) | (long long)i);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) best = min(best, (long long)__shfl_xor(best, o, 64));
+        if (!(gm > thresh)) break;
+        const int bs = (int)(best & 0xffffffffLL);
+        cstar = (int)(best >> 32);
+        if (step == tmax - 1) {
+            if (lane == 0) plist[m] = cstar;
+            ++m;
+            pending = false;
+            break;
         }
+        const int M = m * b;
+        // L_S = chol(W_c*); U = L_S^{-1} H_kc*^T; L_S^{-1}
+        {
+            double w[MAXB];
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j < b) w[j] = g0 ? S.W[(int64_t)bs * bb + j * b + r] : 0.0;
+            bool okS = true;
+            group_chol<MAXB>(w, b, r, g0, gbufs, okS);
+            if (g0) {
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j)
+                    if (j < b) LS[r * b + j] = j <= r ? w[j] : 0.0;
+                if (!okS) sh[3] = 0;
+            }
+            __syncthreads();
+            if (g0) {
+                double x[MAXB], u[MAXB];
+#pragma unroll
+                for (int i = 0; i < MAXB; ++i)
+                    if (i < b) {
+                        double sx = i == r ? 1.0 : 0.0;
+                        double su = S.H[(int64_t)bs * bb + r * b + i];
+#pragma unroll
+                        for (int q = 0; q < MAXB; ++q)
+                            if (q < i) {
+                                sx -= LS[i * b + q] * x[q];
+                                su -= LS[i * b + q] * u[q];
+                            }
+                        x[i] = sx / LS[i * b + i];
+                        u[i] = su / LS[i * b + i];
+                        LSinv[i * b + r] = x[i];
+                        U[i * b + r] = u[i];
+                    }
+            }
+            __syncthreads();
+        }
+        if (!sh[3]) {
+            if (lane == 0) atomicMin(err, k);
+            break;
+        }
+        // H_kk -= U^T U, L_H = chol(H_kk)
+        #pragma unroll 1
+        for (int e = lane; e < bb; e += 64) {
+            const int i = e / b, j = e - i * b;
+            double acc = 0.0;
+            #pragma unroll 1
+            for (int q = 0; q < b; ++q) acc += U[q * b + i] * U[q * b + j];
+            Hkk[e] -= acc;
+        }
+        __syncthreads();
+        {
+            double w[MAXB];
+#pragma unroll
+            for (int j = 0; j < MAXB; ++j)
+                if (j < b) w[j] = g0 ? Hkk[r * b + j] : 0.0;
+            bool okH = true;
+            group_chol<MAXB>(w, b, r, g0, gbufs, okH);
+            if (g0) {
+#pragma unroll
+                for (int j = 0; j < MAXB; ++j)
+                    if (j < b) LH[r * b + j] = j <= r ? w[j] : 0.0;
+                if (!okH) sh[3] = 0;
+            }
+        }
+        // V = Kinv A[P~, c*] (c*'s list holds its nonzero blocks A_jc*)
+        {
+            const int nn = S.nzn[bs];
+            #pragma unroll 1
+            for (int idx = lane; idx < M * b; idx += 64) {
+                const int i = idx / b, s = idx - i * b;
+                double acc = 0.0;
+                #pragma unroll 1
+                for (int t = 0; t < nn; ++t) {
+                    const int pos = S.nzp[(int64_t)bs * AD_MAXP + t];
+                    const int ea = S.nze[(int64_t)bs * AD_MAXP + t];
+                    #pragma unroll 1
+                    for (int q = 0; q < b; ++q)
+                        acc += S.kinv[kidx(i, pos * b + q)] * a_vals[(int64_t)ea * bb + q * b + s];
+                }
+                S.V[idx] = acc;
+            }
+        }
+        __syncthreads();
+        if (!sh[3]) {
+            if (lane == 0) atomicMin(err, k);
+            break;
+        }
+        // Vt = V L_S^{-T}
+        #pragma unroll 1
+        for (int idx = lane; idx < M * b; idx += 64) {
+            const int i = idx / b, s = idx - i * b;
+            double acc = 0.0;
+            #pragma unroll 1
+            for (int q = 0; q <= s; ++q) acc += S.V[(int64_t)i * b + q] * LSinv[s * b + q];
+            S.Vt[idx] = acc;
+        }
+        // candidate list: drop c* (the last slot moves into its place)
+        const int last = ncand - 1;
+        if (bs != last) {
+            #pragma unroll 1
+            for (int e = lane; e < bb; e += 64) {
+                S.W[(int64_t)bs * bb + e] = S.W[(int64_t)last * bb + e];
+                S.H[(int64_t)bs * bb + e] = S.H[(int64_t)last * bb + e];
+            }
+            #pragma unroll 1
+            for (int t = lane; t < AD_MAXP; t += 64) {
+                S.nzp[(int64_t)bs * AD_MAXP + t] = S.nzp[(int64_t)last * AD_MAXP + t];
+                S.nze[(int64_t)bs * AD_MAXP + t] = S.nze[(int64_t)last * AD_MAXP + t];
+            }
+        }
+        __syncthreads();   // V, Vt complete; reads of c*'s slot done
+        if (bs != last && lane == 0) {
+            S.cand[bs] = S.cand[last];
+            S.nzn[bs] = S.nzn[last];
+        }
+        // Kinv <- bordered inverse (packed rows keep their offsets as M grows)
+        {
+            const int64_t tot = ai_tri(M + b);
+            #pragma unroll 1
+            for (int64_t idx = lane; idx < tot; idx += 64) {
+                int i = (int)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
+                while (ai_tri(i + 1) <= idx) ++i;
+                while (ai_tri(i) > idx) --i;
+                const int j = (int)(idx - ai_tri(i));
+                double v;
+                if (i < M) {
+                    double acc = 0.0;
+                    #pragma unroll 1
+                    for (int q = 0; q < b; ++q) acc += S.Vt[(int64_t)i * b + q] * S.Vt[(int64_t)j * b + q];
+                    v = S.kinv[idx] + acc;
+                } else {
+                    const int rr = i - M;
+                    double acc = 0.0;
+                    if (j < M) {
+                        #pragma unroll 1
+                        for (int q = rr; q < b; ++q) acc -= LSinv[q * b + rr] * S.Vt[(int64_t)j * b + q];
+                    } else {
+                        const int ss = j - M;
+                        #pragma unroll 1
+                        for (int q = rr; q < b; ++q) acc += LSinv[q * b + rr] * LSinv[q * b + ss];
+                    }
+                    v = acc;
+                }
+                S.kinv[idx] = v;
+            }
+        }
+        ncand = last;
+        __syncthreads();
+        // candidates brought in by c*: A_c*c != 0, c < k, c not in P_k
+        {
+            const int r0 = a_rowptr[cstar], r1 = a_rowptr[cstar + 1];
+            const int nold = ncand;
+            #pragma unroll 1
+            for (int base = r0; base < r1; base += 64) {
+                const int e = base + lane;
+                bool f = false;
+                int c = -1;
+                if (e < r1) {
+                    c = a_col[e];
+                    f = c < k && c != cstar;
+                    #pragma unroll 1
+                    for (int q = 0; q < m && f; ++q) f = plist[q] != c;
+                    #pragma unroll 1
+                    for (int q = 0; q < nold && f; ++q) f = S.cand[q] != c;
+                }
+                const unsigned long long mk = __ballot(f);
+                if (f) {
+                    const int slot = ncand + __popcll(mk & ((1ull << lane) - 1));
+                    if (slot < cap) {
+                        S.cand[slot] = c;
+                        S.nzn[slot] = 0;
+                    }
+                }
+                ncand += __popcll(mk);
+            }
+            if (ncand > cap) {
+                if (lane == 0) { atomicMin(err, k); sh[3] = 0; }
+                ncand = cap;
+            }
+            __syncthreads();
+            #pragma unroll 1
+            for (int t = lane; t < (ncand - nold) * bb; t += 64) {
+                const int slot = nold + t / bb, e = t % bb;
+                const int c = S.cand[slot];
+                const int ecc = find_block(a_rowptr, a_col, c, c);
+                const int ekc = find_block(a_rowptr, a_col, k, c);
+                S.W[(int64_t)slot * bb + e] = ecc >= 0 ? a_vals[(int64_t)ecc * bb + e] : 0.0;
+                S.H[(int64_t)slot * bb + e] = ekc >= 0 ? a_vals[(int64_t)ekc * bb + e] : 0.0;
+            }
+        }
+        if (lane == 0) plist[m] = cstar;
+        ++m;
+        pending = true;
         __syncthreads();
     }
     // output: sorted P_k (P~ and k)
     if (lane == 0) {
-        const int m = sh[1];
         int tmp[AD_MAXP];
+        #pragma unroll 1
         for (int i = 0; i < m; ++i) tmp[i] = plist[i];
         tmp[m] = k;
+        #pragma unroll 1
         for (int i = 1; i <= m; ++i) {
             int v = tmp[i], j = i - 1;
             while (j >= 0 && tmp[j] > v) { tmp[j + 1] = tmp[j]; --j; }
             tmp[j + 1] = v;
         }
+        #pragma unroll 1
         for (int i = 0; i <= m; ++i) out_cols[(int64_t)k * (tmax + 1) + i] = tmp[i];
         out_cnt[k] = m + 1;
     }
     __syncthreads();
 }
 
-template <int MAXB, int NT>
-__global__ __launch_bounds__(NT) void k_adaptive(int64_t nb, int b, int tmax, double thresh,
+template <int MAXB>
+__global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, double thresh, int cap,
                                                  const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                                  const double* __restrict__ a_vals, int* __restrict__ out_cols,
-                                                 int* __restrict__ out_cnt, int region_lds, int ybuf_lds,
-                                                 int64_t region_doubles, double* scratch, int64_t gstride,
-                                                 int* counter, int* err) {
+                                                 int* __restrict__ out_cnt, int kinv_lds, int v_lds, int Mmax,
+                                                 double* scratch, int64_t gstride, int* counter, int* err) {
     extern __shared__ double lds[];
     __shared__ int plist[AD_MAXP];
-    __shared__ int cand[AD_MAXC];
-    __shared__ double gain[AD_MAXC];
     __shared__ int sh[8];
     __shared__ int next;
-    __shared__ double part[NT];
-    double* greg = scratch + (int64_t)blockIdx.x * gstride;
-    double* reg = region_lds ? lds : greg;
-    double* Ybuf = ybuf_lds ? lds + (region_lds ? region_doubles : 0) : greg + (region_lds ? 0 : region_doubles);
+    const int bb = b * b;
+    const int NB = 64 / b;
+    double* sm = lds;
+    double* gbufs = sm + 5 * bb;
+    double* lfree = gbufs + NB * (3 * bb + 2 * b);
+    double* g = scratch + (int64_t)blockIdx.x * gstride;
+    AiState S;
+    if (kinv_lds) {
+        S.kinv = lfree;
+        lfree += ai_tri(Mmax);
+    } else {
+        S.kinv = g;
+        g += ai_tri(Mmax);
+    }
+    if (v_lds) {
+        S.V = lfree;
+        S.Vt = lfree + (int64_t)Mmax * b;
+    } else {
+        S.V = g;
+        S.Vt = g + (int64_t)Mmax * b;
+        g += 2 * (int64_t)Mmax * b;
+    }
+    S.W = g;
+    S.H = S.W + (int64_t)cap * bb;
+    S.gain = S.H + (int64_t)cap * bb;
+    int* gi = reinterpret_cast<int*>(S.gain + cap);
+    S.cand = gi;
+    S.nzn = gi + cap;
+    S.nzp = gi + 2 * cap;
+    S.nze = S.nzp + (int64_t)cap * AD_MAXP;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
         __syncthreads();
         const int64_t row = next;
         __syncthreads();
         if (row >= nb) break;
-        ad_row<MAXB, NT>((int)row, b, tmax, thresh, a_rowptr, a_col, a_vals, out_cols, out_cnt, reg, Ybuf, plist, cand,
-                     gain, part, sh, err);
+        ai_row<MAXB>((int)row, b, tmax, thresh, cap, a_rowptr, a_col, a_vals, out_cols, out_cnt, S, sm, gbufs, plist,
+                     sh, err);
     }
+}
+
+template <int MAXB>
+static void ai_launch(int64_t grid, size_t dyn, hipStream_t s, int64_t nb, int b, int tmax, double thresh, int cap,
+                      chf_bsr A, int* out_cols, int* out_cnt, int kinv_lds, int v_lds, int Mmax, double* scratch,
+                      int64_t stride, int* counter, int* err) {
+    if (dyn > 64 * 1024)
+        CHF_HIP(hipFuncSetAttribute((const void*)k_adaptive<MAXB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)dyn));
+    hipLaunchKernelGGL(k_adaptive<MAXB>, dim3((unsigned)grid), dim3(64), dyn, s, nb, b, tmax, thresh, cap,
+                       A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, out_cols, out_cnt, kinv_lds, v_lds, Mmax, scratch,
+                       stride, counter, err);
+    CHF_LAUNCH_CHECK();
 }
 
 chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_t s) {
@@ -447,49 +922,57 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
         }
         return P.release();
     }
-    constexpr int NT = 64;   // one wavefront per row: wider workgroups lose more to barriers than they gain
-    const int NB = (NT / 64) * (64 / b);
-    const int Mmax = (tmax - 1) * b;
-    const int64_t region = ad_region_doubles(Mmax, b, NB);
-    const size_t region_bytes = (size_t)region * 8;
-    const size_t ybuf_bytes = (size_t)Mmax * NT * 8;
+    CHF_CHECK(b >= 1 && b <= 32, CHF_EINVAL, "adaptive pattern supports block sizes up to 32");
+    // every candidate lies in the union of the rows A_j, j in P_k
+    int64_t maxrow = 1;
+    for (int64_t k = 0; k < nb; ++k) maxrow = std::max<int64_t>(maxrow, A->rowptr[k + 1] - A->rowptr[k]);
+    const int cap = (int)std::min<int64_t>((int64_t)(tmax + 1) * maxrow, 1 << 20);
+    const int Mmax = (tmax - 1) * b;   // Kinv and V never grow past t_max - 1 blocks
     int dev = 0, lim = 0;
     CHF_HIP(hipGetDevice(&dev));
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t static_lds = AD_MAXP * 4 + AD_MAXC * 12 + 64 + NT * 8;
-    const size_t avail = (size_t)lim > static_lds + 512 ? (size_t)lim - static_lds - 512 : 0;
-    // placement: everything in LDS if it fits, else the right-hand-side buffer
-    // (the operand of the forward substitutions) in LDS, else both in a global slot
-    // LDS only while at least 4 workgroups still fit on a CU: occupancy
-    // matters more than latency for this kernel (measured at 512^2, b = 10:
-    // t_max 8 takes 1.19 s with everything in a global slot at 8 workgroups
-    // per CU, 1.74 s with the right-hand sides in LDS at 3 per CU)
-    const size_t occ = (size_t)lim / 4 > static_lds + 512 ? (size_t)lim / 4 - static_lds - 512 : 0;
-    bool region_lds = region_bytes + ybuf_bytes <= occ;
-    bool ybuf_lds = region_lds || ybuf_bytes <= occ;
-    if (const char* env = std::getenv("CHF_ADAPTIVE_PLACEMENT")) {   // tuning knob: "global" or "region"
-        if (std::string(env) == "global") region_lds = ybuf_lds = false;
-        if (std::string(env) == "region" && region_bytes <= avail) { region_lds = true; ybuf_lds = false; }
+    const size_t static_lds = AD_MAXP * 4 + 8 * 4 + 64;
+    // placement: the per-candidate state always lives in the workgroup's
+    // global slot; Kinv and V / Vt move to LDS only while 8 workgroups still
+    // fit on a CU (one wavefront each: occupancy hides the latency of the
+    // short dependent steps)
+    auto lds_for = [&](bool kl, bool vl) { return (size_t)ai_lds_doubles(Mmax, b, kl, vl) * 8; };
+    const size_t budget = (size_t)lim / 8 > static_lds ? (size_t)lim / 8 - static_lds : 0;
+    bool kinv_lds = lds_for(true, true) <= budget;
+    bool v_lds = kinv_lds || lds_for(false, true) <= budget;
+    if (const char* env = std::getenv("CHF_ADAPTIVE_PLACEMENT")) {   // tuning knob: "global", "v", "all"
+        const std::string p(env);
+        if (p == "global") kinv_lds = v_lds = false;
+        if (p == "v") { kinv_lds = false; v_lds = true; }
+        if (p == "all") kinv_lds = v_lds = true;
     }
-    const size_t dyn = (region_lds ? region_bytes : 0) + (ybuf_lds && !region_lds ? ybuf_bytes : 0) +
-                       (region_lds && ybuf_lds ? ybuf_bytes : 0);
+    const size_t dyn = lds_for(kinv_lds, v_lds);
+    CHF_CHECK(dyn + static_lds <= (size_t)lim, CHF_EINVAL, "adaptive pattern: block size too large for LDS");
     const int cus = device_cu_count();
     const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / (dyn + static_lds + 512)));
     const int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, nb);
-    const int64_t stride = std::max<int64_t>(1, (region_lds ? 0 : region) + (ybuf_lds ? 0 : (int64_t)Mmax * NT));
+    const int64_t stride = (ai_global_doubles(Mmax, b, cap, !kinv_lds, !v_lds) + 31) / 32 * 32;
     DevBuf<double> scratch((size_t)grid * stride);
-    CHF_CHECK(b <= 32, CHF_EINVAL, "adaptive pattern supports block sizes up to 32");
-    auto kern = b == 10 ? k_adaptive<10, NT> : b == 21 ? k_adaptive<21, NT> : k_adaptive<32, NT>;
-    if (dyn > 64 * 1024)
-        CHF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     DevBuf<int> out_cols((size_t)nb * (tmax + 1)), out_cnt(nb), flags(2);
     int init[2] = {0, INT32_MAX};
     flags.upload(init, 2, s);
     const double thresh = -std::log(tau) + AD_GAIN_EPS;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), dyn, s, nb, b, tmax, thresh, A->d_rowptr.p,
-                       A->d_colidx.p, A->d_vals.p, out_cols.p, out_cnt.p, (int)region_lds, (int)ybuf_lds, region,
-                       scratch.p, stride, flags.p, flags.p + 1);
-    CHF_LAUNCH_CHECK();
+    const int ki = kinv_lds ? 1 : 0, vi = v_lds ? 1 : 0;
+    if (b <= 4)
+        ai_launch<4>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
+                     stride, flags.p, flags.p + 1);
+    else if (b <= 10)
+        ai_launch<10>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
+                      stride, flags.p, flags.p + 1);
+    else if (b <= 16)
+        ai_launch<16>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
+                      stride, flags.p, flags.p + 1);
+    else if (b <= 21)
+        ai_launch<21>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
+                      stride, flags.p, flags.p + 1);
+    else
+        ai_launch<32>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
+                      stride, flags.p, flags.p + 1);
     std::vector<int> hcols((size_t)nb * (tmax + 1)), hcnt(nb);
     int hflags[2];
     out_cols.download(hcols.data(), hcols.size(), s);
@@ -498,7 +981,7 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     CHF_HIP(hipStreamSynchronize(s));
     if (hflags[1] != INT32_MAX)
         fail(CHF_ENOTSPD, "adaptive pattern: local matrices of block row " + std::to_string(hflags[1]) +
-                              " are not positive definite (or the candidate list overflowed)");
+                              " are not positive definite");
     for (int64_t k = 0; k < nb; ++k) {
         CHF_CHECK(hcnt[k] >= 1 && hcnt[k] <= tmax + 1, CHF_EDEVICE, "adaptive pattern: bad row count");
         for (int i = 0; i < hcnt[k]; ++i) P->colidx.push_back(hcols[(size_t)k * (tmax + 1) + i]);
@@ -506,7 +989,6 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     }
     return P.release();
 }
-
 }  // namespace chf
 
 extern "C" int chf_pattern_adaptive(chf_bsr A, int tmax, double tau, chf_pattern* out) {

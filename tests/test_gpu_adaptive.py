@@ -23,7 +23,7 @@ def chf():
 
 @pytest.mark.parametrize("n,dim,b,pw,tmax", [
     (9, 2, 1, 2, 4), (12, 2, 3, 2, 6), (11, 2, 10, 2, 8), (7, 2, 21, 3, 8), (5, 3, 10, 2, 6), (10, 2, 10, 2, 0),
-    (6, 2, 2, 2, 20)])
+    (6, 2, 2, 2, 20), (6, 3, 10, 2, 23), (8, 2, 16, 2, 5), (5, 2, 32, 2, 3), (7, 2, 10, 2, 1)])
 def test_adaptive_pattern_bit_exact(chf, n, dim, b, pw, tmax):
     p = make_problem(n, dim, b, pw, seed=0)
     a = from_problem(p)
