@@ -313,67 +313,76 @@ struct AiState {
     double* gain;   // cap
     int* cand;      // cap
     int* nzn;       // cap
+    int* ecs;       // cap: block index of A_c*c for the block added last (-1 if none)
     int* nzp;       // cap x AD_MAXP
     int* nze;       // cap x AD_MAXP
 };
 
 __host__ __device__ inline int64_t ai_global_doubles(int Mmax, int b, int cap, bool kinv_g, bool v_g) {
-    const int64_t ints = (int64_t)cap * (2 + 2 * AD_MAXP);
+    const int64_t ints = (int64_t)cap * (3 + 2 * AD_MAXP);
     return (kinv_g ? ai_tri(Mmax) : 0) + (v_g ? 2 * (int64_t)Mmax * b : 0) + 2 * (int64_t)cap * b * b + cap +
            (ints + 1) / 2;
 }
 
-__host__ __device__ inline int64_t ai_lds_doubles(int Mmax, int b, bool kinv_l, bool v_l) {
+__host__ __device__ inline int64_t ai_small_doubles(int b) { return 5 * (int64_t)b * b + 2 * b; }
+__host__ __device__ inline int64_t ai_group_doubles(int b) { return 3 * (int64_t)b * b + 3 * b; }
+
+__host__ __device__ inline int64_t ai_lds_doubles(int Mmax, int b, int maxrow, bool kinv_l, bool v_l) {
     const int NB = 64 / b;
-    return 5 * (int64_t)b * b + (int64_t)NB * (3 * b * b + 2 * b) + (kinv_l ? ai_tri(Mmax) : 0) +
+    return ai_small_doubles(b) + (int64_t)NB * ai_group_doubles(b) + (maxrow + 1) / 2 + (kinv_l ? ai_tri(Mmax) : 0) +
            (v_l ? 2 * (int64_t)Mmax * b : 0);
 }
 
-// Cholesky of one b x b SPD matrix per group of b lanes; lane r holds row r
-// (w[j] = A[r][j], j <= r) and ends with row r of the factor. One barrier
-// per pivot: the pivot column is published to cb (two alternating buffers of
-// b doubles) and every lane forms its own multipliers. All lanes of the
-// workgroup must call it.
-template <int MAXB>
-__device__ inline void group_chol(double (&w)[MAXB], int b, int r, bool act, double* cb, bool& ok) {
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        if (q < b) {
-            double* c = cb + (q & 1) * b;
-            if (act && r >= q) c[r] = w[q];
-            __syncthreads();
-            if (act && r >= q) {
-                const double d = c[q];
-                ok = ok && d > 0.0 && isfinite(d);
-                const double dd = fmax(d, 1e-300);
-                const double sd = sqrt(dd), inv = 1.0 / dd;
-                const double cr = c[r] * inv;
-                w[q] = r == q ? sd : c[r] / sd;
-#pragma unroll
-                for (int j = 0; j < MAXB; ++j)
-                    if (j > q && j <= r) w[j] -= cr * c[j];
-            }
+// Cholesky of a b x b SPD matrix held row-major in LDS (Mx) by the b lanes of
+// one group: lane r owns row r and ends with row r of the factor in
+// Mx[r][0..r] and 1 / L_rr in rd[r]. One barrier per pivot: the pivot column
+// is published to cb (two alternating buffers of b doubles) and every lane
+// forms its own multipliers. The loops stay rolled so that the square root
+// and the division are emitted once. All lanes of the workgroup call it; it
+// ends with a barrier.
+__device__ inline void group_chol(double* Mx, double* rd, double* cb, int b, int r, bool act, bool& ok) {
+#pragma unroll 1
+    for (int q = 0; q < b; ++q) {
+        double* c = cb + (q & 1) * b;
+        if (act && r >= q) c[r] = Mx[r * b + q];
+        __syncthreads();
+        if (act && r >= q) {
+            const double d = c[q];
+            ok = ok && d > 0.0 && isfinite(d);
+            const double sd = sqrt(fmax(d, 1e-300));
+            const double isd = 1.0 / sd;
+            const double cr = c[r] * isd;   // L_rq
+            Mx[r * b + q] = r == q ? sd : cr;
+            if (r == q) rd[r] = isd;
+            const double crs = cr * isd;    // c_r / d
+#pragma unroll 1
+            for (int j = q + 1; j <= r; ++j) Mx[r * b + j] -= crs * c[j];
         }
     }
+    __syncthreads();
 }
 
 // One pass over the candidates in slots [s0, s0 + cnt): apply the pending
 // update of the block added last (when `pending`), then g_c = -log rho_c.
-// Lane (ci, r) works on candidate s0 + ci, row/column r of its blocks.
-template <int MAXB>
-__device__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar, int mold,
-                         const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
-                         const double* __restrict__ a_vals, const AiState& S, const double* V, const double* LSinv,
-                         const double* U, const double* LH, double* gbufs, int* flag) {
+// Lane (ci, r) works on candidate s0 + ci, row/column r of its blocks. BC > 0
+// fixes the block size at compile time.
+template <int MAXB, int BC>
+__device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar, int mold,
+                                         const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
+                                         const double* __restrict__ a_vals, const AiState& S, const double* V,
+                                         const double* LSinv, const double* U, const double* LH,
+                                         const double* LHrd, double* gbufs, int* flag) {
+    if (BC > 0) b = BC;
     const int lane = threadIdx.x;
     const int bb = b * b;
     const int ci = lane / b, r = lane - ci * b;
     const bool act = ci < cnt;
     const int slot = s0 + ci;
-    double* cb = gbufs + (act ? ci : 0) * (3 * bb + 2 * b);
-    double* B1 = cb + 2 * b;   // e_c, then Z
-    double* BL = B1 + bb;      // L_W
-    double* BX = BL + bb;      // X
+    double* cb = gbufs + (act ? ci : 0) * ai_group_doubles(b);
+    double* rd = cb + 2 * b;   // 1 / diagonal of L_W
+    double* BW = rd + b;       // W_c by rows, then L_W
+    double* B1 = BW + bb;      // e_c by columns, then Z by columns, then N by rows
+    double* BX = B1 + bb;      // X by columns
     double w[MAXB], h[MAXB];
     __syncthreads();
     if (act) {
@@ -385,29 +394,45 @@ __device__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar,
             }
     }
     if (pending) {
-        double et[MAXB];
+        double et[MAXB], e[MAXB];
         int ecs = -1, nn = 0;
         if (act) {
-            const int c = S.cand[slot];
-            ecs = find_block(a_rowptr, a_col, cstar, c);
-            double e[MAXB];
+            ecs = S.ecs[slot];
 #pragma unroll
             for (int i = 0; i < MAXB; ++i)
                 if (i < b) e[i] = ecs >= 0 ? a_vals[(int64_t)ecs * bb + i * b + r] : 0.0;
             nn = S.nzn[slot];
-            #pragma unroll 1
-            for (int t = 0; t < nn; ++t) {
+        }
+        // E_c -= V_j^T A_jc over the blocks j of P~ next to c; each V_j block
+        // (b x b) is staged through the group's LDS buffer by rows (the trip
+        // count is made uniform across the wavefront for the barriers)
+        int nmax = act ? nn : 0;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+#pragma unroll 1
+        for (int t = 0; t < nmax; ++t) {
+            const bool live = act && t < nn;
+            int ea = 0;
+            if (live) {
                 const int pos = S.nzp[(int64_t)slot * AD_MAXP + t];
-                const int ea = S.nze[(int64_t)slot * AD_MAXP + t];
-                #pragma unroll 1
+                ea = S.nze[(int64_t)slot * AD_MAXP + t];
+                const double* vr = V + (int64_t)(pos * b + r) * b;
+#pragma unroll
+                for (int i = 0; i < MAXB; ++i)
+                    if (i < b) BX[r * b + i] = vr[i];
+            }
+            __syncthreads();
+            if (live) {
                 for (int q = 0; q < b; ++q) {
                     const double aq = a_vals[(int64_t)ea * bb + q * b + r];
-                    const double* vr = V + (int64_t)(pos * b + q) * b;
 #pragma unroll
                     for (int i = 0; i < MAXB; ++i)
-                        if (i < b) e[i] -= vr[i] * aq;
+                        if (i < b) e[i] -= BX[q * b + i] * aq;
                 }
             }
+            __syncthreads();
+        }
+        if (act) {
 #pragma unroll
             for (int i = 0; i < MAXB; ++i)
                 if (i < b) {
@@ -443,21 +468,25 @@ __device__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar,
             }
         }
     }
-    // L_W = chol(W_c)
-    bool ok = true;
-    group_chol<MAXB>(w, b, r, act, cb, ok);
+    // L_W = chol(W_c); W_c is symmetric, so column r is row r
     if (act) {
-        // rows of L_W; Z = L_H^{-1} H_kc, column r
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i)
+            if (i < b) BW[r * b + i] = w[i];
+    }
+    bool ok = true;
+    group_chol(BW, rd, cb, b, r, act, ok);
+    if (act) {
+        // Z = L_H^{-1} H_kc, column r
         double z[MAXB];
 #pragma unroll
         for (int i = 0; i < MAXB; ++i)
             if (i < b) {
-                BL[r * b + i] = i <= r ? w[i] : 0.0;
                 double s = h[i];
 #pragma unroll
                 for (int q = 0; q < MAXB; ++q)
                     if (q < i) s -= LH[i * b + q] * z[q];
-                z[i] = s / LH[i * b + i];
+                z[i] = s * LHrd[i];
                 B1[i * b + r] = z[i];
             }
     }
@@ -471,15 +500,14 @@ __device__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar,
                 double s = B1[r * b + i];
 #pragma unroll
                 for (int q = 0; q < MAXB; ++q)
-                    if (q < i) s -= BL[i * b + q] * x[q];
-                x[i] = s / BL[i * b + i];
+                    if (q < i) s -= BW[i * b + q] * x[q];
+                x[i] = s * rd[i];
                 BX[i * b + r] = x[i];
             }
     }
     __syncthreads();
-    // row r of N = X X^T (lower part)
-    double n[MAXB];
     if (act) {
+        // row r of N = X X^T, lower part
         double xr[MAXB];
 #pragma unroll
         for (int q = 0; q < MAXB; ++q)
@@ -491,29 +519,26 @@ __device__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar,
 #pragma unroll
                 for (int q = 0; q < MAXB; ++q)
                     if (q < b) acc += xr[q] * BX[s * b + q];
-                n[s] = acc;
+                B1[r * b + s] = acc;
             }
     }
     // -log det(I - N): Cholesky of I - N carried on N (the pivot of step q is
     // 1 - s_q with s_q the current N_qq, logged as log1p(-s_q)); every lane
-    // sees every pivot and accumulates the sum itself.
+    // sees every pivot and accumulates the sum itself
     double lg = 0.0;
-#pragma unroll
-    for (int q = 0; q < MAXB; ++q) {
-        if (q < b) {
-            double* c = cb + (q & 1) * b;
-            if (act && r >= q) c[r] = n[q];
-            __syncthreads();
-            if (act) {
-                const double sq = c[q];
-                ok = ok && sq < 1.0;
-                lg += log1p(-sq);
-                if (r > q) {
-                    const double cr = c[r] / fmax(1.0 - sq, 1e-300);
-#pragma unroll
-                    for (int j = 0; j < MAXB; ++j)
-                        if (j > q && j <= r) n[j] += cr * c[j];
-                }
+#pragma unroll 1
+    for (int q = 0; q < b; ++q) {
+        double* c = cb + (q & 1) * b;
+        if (act && r >= q) c[r] = B1[r * b + q];
+        __syncthreads();
+        if (act) {
+            const double sq = c[q];
+            ok = ok && sq < 1.0;
+            lg += log1p(-sq);
+            if (r > q) {
+                const double cr = c[r] / fmax(1.0 - sq, 1e-300);
+#pragma unroll 1
+                for (int j = q + 1; j <= r; ++j) B1[r * b + j] += cr * c[j];
             }
         }
     }
@@ -521,11 +546,39 @@ __device__ void ai_batch(int k, int b, int s0, int cnt, bool pending, int cstar,
     if (act && !ok) *flag = 0;
 }
 
-template <int MAXB>
-__device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int* __restrict__ a_rowptr,
+// W_c = A_cc, H_kc = A_kc for the candidates in slots [s0, s1): one search
+// of row c and row k per candidate, then the blocks are copied by all lanes.
+__device__ inline void ai_init_slots(int k, int b, int s0, int s1, const int* __restrict__ a_rowptr,
+                                     const int* __restrict__ a_col, const double* __restrict__ a_vals,
+                                     const AiState& S, int* tmp_a, int* tmp_b) {
+    const int lane = threadIdx.x;
+    const int bb = b * b;
+#pragma unroll 1
+    for (int c0 = s0; c0 < s1; c0 += 64) {
+        const int n = min(64, s1 - c0);
+        if (lane < n) {
+            const int c = S.cand[c0 + lane];
+            tmp_a[lane] = find_block(a_rowptr, a_col, c, c);
+            tmp_b[lane] = find_block(a_rowptr, a_col, k, c);
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int t = lane; t < n * bb; t += 64) {
+            const int sl = t / bb, e = t - sl * bb;
+            const int ecc = tmp_a[sl], ekc = tmp_b[sl];
+            S.W[(int64_t)(c0 + sl) * bb + e] = ecc >= 0 ? a_vals[(int64_t)ecc * bb + e] : 0.0;
+            S.H[(int64_t)(c0 + sl) * bb + e] = ekc >= 0 ? a_vals[(int64_t)ekc * bb + e] : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+template <int MAXB, int BC>
+__device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int* __restrict__ a_rowptr,
                        const int* __restrict__ a_col, const double* __restrict__ a_vals, int* __restrict__ out_cols,
-                       int* __restrict__ out_cnt, const AiState& S, double* sm, double* gbufs, int* plist, int* sh,
-                       int* err) {
+                       int* __restrict__ out_cnt, const AiState& S, double* sm, double* gbufs, int* mark,
+                       int* plist, int* tmp_a, int* tmp_b, int* sh, int* err) {
+    if (BC > 0) b = BC;
     const int lane = threadIdx.x;
     const int bb = b * b;
     const int NB = 64 / b;
@@ -534,6 +587,8 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
     double* LS = LH + bb;
     double* LSinv = LS + bb;
     double* U = LSinv + bb;
+    double* LHrd = U + bb;      // 1 / diagonal of L_H
+    double* LSrd = LHrd + b;    // 1 / diagonal of L_S
     const bool g0 = lane < b;   // group 0 does the single b x b factorisations
     const int r = lane;
     // H_kk = A_kk, L_H; candidates: A_kc != 0, c < k, with W_c = A_cc, H_kc = A_kc
@@ -564,28 +619,13 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
         if (lane == 0) atomicMin(err, k);
         ncand = 0;
     }
-    #pragma unroll 1
-    for (int t = lane; t < ncand * bb; t += 64) {
-        const int slot = t / bb, e = t - slot * bb;
-        const int c = S.cand[slot];
-        const int ecc = find_block(a_rowptr, a_col, c, c);
-        const int ekc = find_block(a_rowptr, a_col, k, c);
-        S.W[(int64_t)slot * bb + e] = ecc >= 0 ? a_vals[(int64_t)ecc * bb + e] : 0.0;
-        S.H[(int64_t)slot * bb + e] = ekc >= 0 ? a_vals[(int64_t)ekc * bb + e] : 0.0;
-    }
+    ai_init_slots(k, b, 0, ncand, a_rowptr, a_col, a_vals, S, tmp_a, tmp_b);
     bool ok = true;
-    {
-        double w[MAXB];
-#pragma unroll
-        for (int j = 0; j < MAXB; ++j)
-            if (j < b) w[j] = g0 ? Hkk[r * b + j] : 0.0;
-        group_chol<MAXB>(w, b, r, g0, gbufs, ok);
-        if (g0)
-#pragma unroll
-            for (int j = 0; j < MAXB; ++j)
-                if (j < b) LH[r * b + j] = j <= r ? w[j] : 0.0;
-        if (g0 && !ok) sh[3] = 0;
-    }
+    if (g0)
+#pragma unroll 1
+        for (int j = 0; j < b; ++j) LH[r * b + j] = Hkk[r * b + j];
+    group_chol(LH, LHrd, gbufs, b, r, g0, ok);
+    if (g0 && !ok) sh[3] = 0;
     __syncthreads();
     if (!sh[3]) {
         if (lane == 0) atomicMin(err, k);
@@ -598,8 +638,8 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
         if (ncand == 0) break;
         #pragma unroll 1
         for (int s0 = 0; s0 < ncand; s0 += NB)
-            ai_batch<MAXB>(k, b, s0, min(NB, ncand - s0), pending, cstar, m - 1, a_rowptr, a_col, a_vals, S, S.V,
-                           LSinv, U, LH, gbufs, sh + 3);
+            ai_batch<MAXB, BC>(k, b, s0, min(NB, ncand - s0), pending, cstar, m - 1, a_rowptr, a_col, a_vals, S, S.V,
+                               LSinv, U, LH, LHrd, gbufs, sh + 3);
         __syncthreads();
         if (!sh[3]) {
             if (lane == 0) atomicMin(err, k);
@@ -631,19 +671,12 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
         const int M = m * b;
         // L_S = chol(W_c*); U = L_S^{-1} H_kc*^T; L_S^{-1}
         {
-            double w[MAXB];
-#pragma unroll
-            for (int j = 0; j < MAXB; ++j)
-                if (j < b) w[j] = g0 ? S.W[(int64_t)bs * bb + j * b + r] : 0.0;
+            if (g0)
+#pragma unroll 1
+                for (int j = 0; j < b; ++j) LS[r * b + j] = S.W[(int64_t)bs * bb + j * b + r];
             bool okS = true;
-            group_chol<MAXB>(w, b, r, g0, gbufs, okS);
-            if (g0) {
-#pragma unroll
-                for (int j = 0; j < MAXB; ++j)
-                    if (j < b) LS[r * b + j] = j <= r ? w[j] : 0.0;
-                if (!okS) sh[3] = 0;
-            }
-            __syncthreads();
+            group_chol(LS, LSrd, gbufs, b, r, g0, okS);
+            if (g0 && !okS) sh[3] = 0;
             if (g0) {
                 double x[MAXB], u[MAXB];
 #pragma unroll
@@ -657,10 +690,11 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
                                 sx -= LS[i * b + q] * x[q];
                                 su -= LS[i * b + q] * u[q];
                             }
-                        x[i] = sx / LS[i * b + i];
-                        u[i] = su / LS[i * b + i];
+                        x[i] = sx * LSrd[i];
+                        u[i] = su * LSrd[i];
                         LSinv[i * b + r] = x[i];
                         U[i * b + r] = u[i];
+                        __builtin_amdgcn_sched_barrier(0);
                     }
             }
             __syncthreads();
@@ -674,24 +708,17 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
         for (int e = lane; e < bb; e += 64) {
             const int i = e / b, j = e - i * b;
             double acc = 0.0;
-            #pragma unroll 1
-            for (int q = 0; q < b; ++q) acc += U[q * b + i] * U[q * b + j];
+                        for (int q = 0; q < b; ++q) acc += U[q * b + i] * U[q * b + j];
             Hkk[e] -= acc;
         }
         __syncthreads();
         {
-            double w[MAXB];
-#pragma unroll
-            for (int j = 0; j < MAXB; ++j)
-                if (j < b) w[j] = g0 ? Hkk[r * b + j] : 0.0;
+            if (g0)
+#pragma unroll 1
+                for (int j = 0; j < b; ++j) LH[r * b + j] = Hkk[r * b + j];
             bool okH = true;
-            group_chol<MAXB>(w, b, r, g0, gbufs, okH);
-            if (g0) {
-#pragma unroll
-                for (int j = 0; j < MAXB; ++j)
-                    if (j < b) LH[r * b + j] = j <= r ? w[j] : 0.0;
-                if (!okH) sh[3] = 0;
-            }
+            group_chol(LH, LHrd, gbufs, b, r, g0, okH);
+            if (g0 && !okH) sh[3] = 0;
         }
         // V = Kinv A[P~, c*] (c*'s list holds its nonzero blocks A_jc*)
         {
@@ -704,8 +731,7 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
                 for (int t = 0; t < nn; ++t) {
                     const int pos = S.nzp[(int64_t)bs * AD_MAXP + t];
                     const int ea = S.nze[(int64_t)bs * AD_MAXP + t];
-                    #pragma unroll 1
-                    for (int q = 0; q < b; ++q)
+                                        for (int q = 0; q < b; ++q)
                         acc += S.kinv[kidx(i, pos * b + q)] * a_vals[(int64_t)ea * bb + q * b + s];
                 }
                 S.V[idx] = acc;
@@ -721,33 +747,43 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
         for (int idx = lane; idx < M * b; idx += 64) {
             const int i = idx / b, s = idx - i * b;
             double acc = 0.0;
-            #pragma unroll 1
-            for (int q = 0; q <= s; ++q) acc += S.V[(int64_t)i * b + q] * LSinv[s * b + q];
+                        for (int q = 0; q <= s; ++q) acc += S.V[(int64_t)i * b + q] * LSinv[s * b + q];
             S.Vt[idx] = acc;
         }
         // candidate list: drop c* (the last slot moves into its place)
         const int last = ncand - 1;
         if (bs != last) {
-            #pragma unroll 1
             for (int e = lane; e < bb; e += 64) {
                 S.W[(int64_t)bs * bb + e] = S.W[(int64_t)last * bb + e];
                 S.H[(int64_t)bs * bb + e] = S.H[(int64_t)last * bb + e];
             }
-            #pragma unroll 1
             for (int t = lane; t < AD_MAXP; t += 64) {
                 S.nzp[(int64_t)bs * AD_MAXP + t] = S.nzp[(int64_t)last * AD_MAXP + t];
                 S.nze[(int64_t)bs * AD_MAXP + t] = S.nze[(int64_t)last * AD_MAXP + t];
             }
         }
-        __syncthreads();   // V, Vt complete; reads of c*'s slot done
+        const int r0 = a_rowptr[cstar], r1 = a_rowptr[cstar + 1];
+#pragma unroll 1
+        for (int e = lane; e < r1 - r0; e += 64) mark[e] = 0;
+        __syncthreads();   // V, Vt complete; reads of c*'s slot done; marks clear
         if (bs != last && lane == 0) {
             S.cand[bs] = S.cand[last];
             S.nzn[bs] = S.nzn[last];
         }
+        ncand = last;
+        __syncthreads();
+        // A_c*c for every remaining candidate (one search of row c* each);
+        // the entries of row c* found this way are marked
+#pragma unroll 1
+        for (int q = lane; q < ncand; q += 64) {
+            const int e = find_block(a_rowptr, a_col, cstar, S.cand[q]);
+            S.ecs[q] = e;
+            if (e >= 0) mark[e - r0] = 1;
+        }
         // Kinv <- bordered inverse (packed rows keep their offsets as M grows)
         {
             const int64_t tot = ai_tri(M + b);
-            #pragma unroll 1
+#pragma unroll 1
             for (int64_t idx = lane; idx < tot; idx += 64) {
                 int i = (int)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
                 while (ai_tri(i + 1) <= idx) ++i;
@@ -756,18 +792,15 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
                 double v;
                 if (i < M) {
                     double acc = 0.0;
-                    #pragma unroll 1
                     for (int q = 0; q < b; ++q) acc += S.Vt[(int64_t)i * b + q] * S.Vt[(int64_t)j * b + q];
                     v = S.kinv[idx] + acc;
                 } else {
                     const int rr = i - M;
                     double acc = 0.0;
                     if (j < M) {
-                        #pragma unroll 1
                         for (int q = rr; q < b; ++q) acc -= LSinv[q * b + rr] * S.Vt[(int64_t)j * b + q];
                     } else {
                         const int ss = j - M;
-                        #pragma unroll 1
                         for (int q = rr; q < b; ++q) acc += LSinv[q * b + rr] * LSinv[q * b + ss];
                     }
                     v = acc;
@@ -775,24 +808,21 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
                 S.kinv[idx] = v;
             }
         }
-        ncand = last;
         __syncthreads();
-        // candidates brought in by c*: A_c*c != 0, c < k, c not in P_k
+        // candidates brought in by c*: unmarked entries of row c* left of k,
+        // other than c* and the blocks of P~
         {
-            const int r0 = a_rowptr[cstar], r1 = a_rowptr[cstar + 1];
             const int nold = ncand;
-            #pragma unroll 1
+#pragma unroll 1
             for (int base = r0; base < r1; base += 64) {
                 const int e = base + lane;
                 bool f = false;
                 int c = -1;
                 if (e < r1) {
                     c = a_col[e];
-                    f = c < k && c != cstar;
-                    #pragma unroll 1
+                    f = c < k && c != cstar && !mark[e - r0];
+#pragma unroll 1
                     for (int q = 0; q < m && f; ++q) f = plist[q] != c;
-                    #pragma unroll 1
-                    for (int q = 0; q < nold && f; ++q) f = S.cand[q] != c;
                 }
                 const unsigned long long mk = __ballot(f);
                 if (f) {
@@ -800,6 +830,7 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
                     if (slot < cap) {
                         S.cand[slot] = c;
                         S.nzn[slot] = 0;
+                        S.ecs[slot] = e;
                     }
                 }
                 ncand += __popcll(mk);
@@ -809,15 +840,7 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
                 ncand = cap;
             }
             __syncthreads();
-            #pragma unroll 1
-            for (int t = lane; t < (ncand - nold) * bb; t += 64) {
-                const int slot = nold + t / bb, e = t % bb;
-                const int c = S.cand[slot];
-                const int ecc = find_block(a_rowptr, a_col, c, c);
-                const int ekc = find_block(a_rowptr, a_col, k, c);
-                S.W[(int64_t)slot * bb + e] = ecc >= 0 ? a_vals[(int64_t)ecc * bb + e] : 0.0;
-                S.H[(int64_t)slot * bb + e] = ekc >= 0 ? a_vals[(int64_t)ekc * bb + e] : 0.0;
-            }
+            ai_init_slots(k, b, nold, ncand, a_rowptr, a_col, a_vals, S, tmp_a, tmp_b);
         }
         if (lane == 0) plist[m] = cstar;
         ++m;
@@ -843,21 +866,25 @@ __device__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int
     __syncthreads();
 }
 
-template <int MAXB>
+template <int MAXB, int BC>
 __global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, double thresh, int cap,
                                                  const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                                  const double* __restrict__ a_vals, int* __restrict__ out_cols,
                                                  int* __restrict__ out_cnt, int kinv_lds, int v_lds, int Mmax,
-                                                 double* scratch, int64_t gstride, int* counter, int* err) {
+                                                 int maxrow, double* scratch, int64_t gstride, int* counter,
+                                                 int* err) {
+    if (BC > 0) b = BC;
     extern __shared__ double lds[];
     __shared__ int plist[AD_MAXP];
     __shared__ int sh[8];
     __shared__ int next;
+    __shared__ int tmp_a[64], tmp_b[64];
     const int bb = b * b;
     const int NB = 64 / b;
     double* sm = lds;
-    double* gbufs = sm + 5 * bb;
-    double* lfree = gbufs + NB * (3 * bb + 2 * b);
+    double* gbufs = sm + ai_small_doubles(b);
+    int* mark = reinterpret_cast<int*>(gbufs + NB * ai_group_doubles(b));
+    double* lfree = gbufs + NB * ai_group_doubles(b) + (maxrow + 1) / 2;
     double* g = scratch + (int64_t)blockIdx.x * gstride;
     AiState S;
     if (kinv_lds) {
@@ -881,7 +908,8 @@ __global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, do
     int* gi = reinterpret_cast<int*>(S.gain + cap);
     S.cand = gi;
     S.nzn = gi + cap;
-    S.nzp = gi + 2 * cap;
+    S.ecs = gi + 2 * cap;
+    S.nzp = gi + 3 * cap;
     S.nze = S.nzp + (int64_t)cap * AD_MAXP;
     for (;;) {
         if (threadIdx.x == 0) next = atomicAdd(counter, 1);
@@ -889,21 +917,21 @@ __global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, do
         const int64_t row = next;
         __syncthreads();
         if (row >= nb) break;
-        ai_row<MAXB>((int)row, b, tmax, thresh, cap, a_rowptr, a_col, a_vals, out_cols, out_cnt, S, sm, gbufs, plist,
-                     sh, err);
+        ai_row<MAXB, BC>((int)row, b, tmax, thresh, cap, a_rowptr, a_col, a_vals, out_cols, out_cnt, S, sm, gbufs, mark,
+                         plist, tmp_a, tmp_b, sh, err);
     }
 }
 
-template <int MAXB>
+template <int MAXB, int BC>
 static void ai_launch(int64_t grid, size_t dyn, hipStream_t s, int64_t nb, int b, int tmax, double thresh, int cap,
-                      chf_bsr A, int* out_cols, int* out_cnt, int kinv_lds, int v_lds, int Mmax, double* scratch,
-                      int64_t stride, int* counter, int* err) {
+                      chf_bsr A, int* out_cols, int* out_cnt, int kinv_lds, int v_lds, int Mmax, int maxrow,
+                      double* scratch, int64_t stride, int* counter, int* err) {
+    auto kern = k_adaptive<MAXB, BC>;
     if (dyn > 64 * 1024)
-        CHF_HIP(hipFuncSetAttribute((const void*)k_adaptive<MAXB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)dyn));
-    hipLaunchKernelGGL(k_adaptive<MAXB>, dim3((unsigned)grid), dim3(64), dyn, s, nb, b, tmax, thresh, cap,
-                       A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, out_cols, out_cnt, kinv_lds, v_lds, Mmax, scratch,
-                       stride, counter, err);
+        CHF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), dyn, s, nb, b, tmax, thresh, cap,
+                       A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, out_cols, out_cnt, kinv_lds, v_lds, Mmax, maxrow,
+                       scratch, stride, counter, err);
     CHF_LAUNCH_CHECK();
 }
 
@@ -931,12 +959,12 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     int dev = 0, lim = 0;
     CHF_HIP(hipGetDevice(&dev));
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-    const size_t static_lds = AD_MAXP * 4 + 8 * 4 + 64;
+    const size_t static_lds = AD_MAXP * 4 + 8 * 4 + 64 + 2 * 64 * 4;
     // placement: the per-candidate state always lives in the workgroup's
     // global slot; Kinv and V / Vt move to LDS only while 8 workgroups still
     // fit on a CU (one wavefront each: occupancy hides the latency of the
     // short dependent steps)
-    auto lds_for = [&](bool kl, bool vl) { return (size_t)ai_lds_doubles(Mmax, b, kl, vl) * 8; };
+    auto lds_for = [&](bool kl, bool vl) { return (size_t)ai_lds_doubles(Mmax, b, (int)maxrow, kl, vl) * 8; };
     const size_t budget = (size_t)lim / 8 > static_lds ? (size_t)lim / 8 - static_lds : 0;
     bool kinv_lds = lds_for(true, true) <= budget;
     bool v_lds = kinv_lds || lds_for(false, true) <= budget;
@@ -958,21 +986,19 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     flags.upload(init, 2, s);
     const double thresh = -std::log(tau) + AD_GAIN_EPS;
     const int ki = kinv_lds ? 1 : 0, vi = v_lds ? 1 : 0;
-    if (b <= 4)
-        ai_launch<4>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
-                     stride, flags.p, flags.p + 1);
-    else if (b <= 10)
-        ai_launch<10>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
-                      stride, flags.p, flags.p + 1);
-    else if (b <= 16)
-        ai_launch<16>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
-                      stride, flags.p, flags.p + 1);
-    else if (b <= 21)
-        ai_launch<21>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
-                      stride, flags.p, flags.p + 1);
-    else
-        ai_launch<32>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, scratch.p,
-                      stride, flags.p, flags.p + 1);
+    // the block sizes of the workloads get their own instantiation (block
+    // offsets are compile-time constants); others share one per size class
+#define CHF_AI_LAUNCH(MB, BCV)                                                                                   \
+    ai_launch<MB, BCV>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, (int)maxrow, \
+                       scratch.p, stride, flags.p, flags.p + 1)
+    if (b == 10) CHF_AI_LAUNCH(10, 10);
+    else if (b == 21) CHF_AI_LAUNCH(21, 21);
+    else if (b <= 4) CHF_AI_LAUNCH(4, 0);
+    else if (b <= 10) CHF_AI_LAUNCH(10, 0);
+    else if (b <= 16) CHF_AI_LAUNCH(16, 0);
+    else if (b <= 21) CHF_AI_LAUNCH(21, 0);
+    else CHF_AI_LAUNCH(32, 0);
+#undef CHF_AI_LAUNCH
     std::vector<int> hcols((size_t)nb * (tmax + 1)), hcnt(nb);
     int hflags[2];
     out_cols.download(hcols.data(), hcols.size(), s);
