@@ -409,13 +409,23 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
         int nmax = act ? nn : 0;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
+        // lane r of a group holds list entry r (one load for the first b entries)
+        const int g0l = lane - r;
+        int my_pos = 0, my_ea = 0;
+        if (act && r < nn) {
+            my_pos = S.nzp[(int64_t)slot * AD_MAXP + r];
+            my_ea = S.nze[(int64_t)slot * AD_MAXP + r];
+        }
 #pragma unroll 1
         for (int t = 0; t < nmax; ++t) {
             const bool live = act && t < nn;
-            int ea = 0;
-            if (live) {
-                const int pos = S.nzp[(int64_t)slot * AD_MAXP + t];
+            int pos = __shfl(my_pos, g0l + min(t, b - 1), 64);
+            int ea = __shfl(my_ea, g0l + min(t, b - 1), 64);
+            if (live && t >= b) {
+                pos = S.nzp[(int64_t)slot * AD_MAXP + t];
                 ea = S.nze[(int64_t)slot * AD_MAXP + t];
+            }
+            if (live) {
                 const double* vr = V + (int64_t)(pos * b + r) * b;
 #pragma unroll
                 for (int i = 0; i < MAXB; ++i)
