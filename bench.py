@@ -60,7 +60,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-setup3d", action="store_true")
-    ap.add_argument("--setup3d-grid", type=int, default=32, help="3D patch grid of the batched set-up leg")
+    ap.add_argument("--setup3d-grid", type=int, default=64, help="3D patch grid of the batched set-up leg")
     ap.add_argument("--setup3d-tmax", type=int, default=23)
     ap.add_argument("--only-setup3d", action="store_true",
                     help="run only the batched 3D set-up leg (for hardware-counter passes)")
