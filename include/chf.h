@@ -42,6 +42,8 @@ typedef enum {
 } chf_status;
 
 typedef enum { CHF_F64 = 0, CHF_F32 = 1, CHF_BF16 = 2 } chf_dtype;
+typedef enum { CHF_SMOOTH_CHEB4 = 0, CHF_SMOOTH_CHEB1 = 1, CHF_SMOOTH_RICHARDSON = 2 } chf_smoother;
+typedef enum { CHF_CYCLE_VKK = 0, CHF_CYCLE_V2K0 = 1 } chf_cycle;
 
 typedef struct chf_bsr_s* chf_bsr;
 typedef struct chf_pattern_s* chf_pattern;
@@ -121,6 +123,19 @@ int chf_lmax_lanczos(chf_bsr A, chf_fsai G, chf_dtype dtype, int iters, const do
 int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree,
                      const void* b, void* x, int x_is_zero, void* work, hipStream_t stream);
 
+/* Comparators of Sec. 3.2, with the same arguments, layout and work buffer
+ * as chf_cheb4_smooth:
+ * - chf_cheb1_smooth: Algorithm 2 (Chebyshev iteration of the first kind)
+ *   with the preconditioner M, on the smoothing interval [alpha, beta]
+ *   (0 < alpha < beta; Sec. 3.2 takes alpha = rho lambda_max, rho in (0,1)).
+ * - chf_richardson_smooth: Richardson smoothing x <- x + omega M (b - A x),
+ *   `degree` times, i.e. S = (I - omega M A)^degree (omega = 1 in Sec. 3.2).
+ * EINVAL for degree < 1 or parameters outside these ranges. */
+int chf_cheb1_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double alpha, double beta, int degree,
+                     const void* b, void* x, int x_is_zero, void* work, hipStream_t stream);
+int chf_richardson_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double omega, int degree,
+                          const void* b, void* x, int x_is_zero, void* work, hipStream_t stream);
+
 /* ----------------------------------------------------------- V-cycle ---- */
 typedef struct {
     int degree;          /* Chebyshev degree k of V(k,k) */
@@ -158,12 +173,21 @@ int chf_levels_info(chf_levels L, int* nlevels, int64_t* nb_per_level /* [nlevel
 int chf_levels_get(chf_levels L, int level, chf_bsr* A, chf_fsai* G, chf_pattern* P);
 int chf_levels_get_beta(chf_levels L, int level, double* beta);
 int chf_levels_set_beta(chf_levels L, int level, double beta);
-/* One V(k,k) cycle on level 0: x <- V(b, x); vectors of the hierarchy's
- * working dtype (double for F64, float otherwise). */
+/* Smoother and cycle shape of the hierarchy (default: fourth kind, V(k,k)).
+ * smoother: CHF_SMOOTH_CHEB4 (Algorithm 3 on [0, beta_l]; param ignored),
+ * CHF_SMOOTH_CHEB1 (Algorithm 2 on [param * beta_l, beta_l], 0 < param < 1),
+ * CHF_SMOOTH_RICHARDSON (omega = param > 0). cycle: CHF_CYCLE_VKK, or
+ * CHF_CYCLE_V2K0 (Sec. 5's non-symmetric cycle: one pre-smoothing application
+ * of degree 2k and no post-smoothing; PCG then requires the flexible form).
+ * May be called before or after chf_levels_setup; the bounds beta_l stay. */
+int chf_levels_set_cycle(chf_levels L, chf_smoother smoother, double param, chf_cycle cycle);
+/* One cycle (V(k,k), or V(2k,0) when so set) on level 0: x <- V(b, x);
+ * vectors of the hierarchy's working dtype (double for F64, float otherwise). */
 int chf_vcycle(chf_levels L, const void* b, void* x, int x_is_zero, hipStream_t stream);
-/* FP64 PCG from x = 0 with one V(k,k) cycle as preconditioner (cast to and
- * from the working dtype for mixed hierarchies). Stops when the recursive
- * residual ||r|| <= rtol ||b||. flexible != 0: Polak-Ribiere beta.
+/* FP64 PCG from x = 0 with one cycle as preconditioner (cast to and from
+ * the working dtype for mixed hierarchies). Stops when the recursive
+ * residual ||r|| <= rtol ||b||. flexible != 0: Polak-Ribiere beta (required,
+ * else EINVAL, when the cycle is V(2k,0), which is not symmetric).
  * relres_hist (host, maxit+1, may be NULL) receives ||r_i||/||b||;
  * true_relres (may be NULL) receives ||b - A x|| / ||b|| in FP64.
  * ENOCONV if maxit is reached (x holds the last iterate). */

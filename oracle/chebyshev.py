@@ -1,8 +1,13 @@
-"""Fourth-kind Chebyshev smoothing (paper Sec. 3.1, Algorithm 3).
+"""Polynomial smoothers of Sec. 3: fourth-kind Chebyshev (Algorithm 3), and
+the comparators of Sec. 3.2, first-kind Chebyshev (Algorithm 2) and
+Richardson smoothing S = (I - omega M A)^k.
 
-``cheb4`` follows Algorithm 3 step by step. ``w4`` and ``w4_hat`` evaluate the
-polynomials of Eq. chebyshev_4th_kind through the three-term recurrence that
-follows it; they serve the pins in the tests.
+``cheb4``, ``cheb1`` and ``richardson`` follow their algorithms step by step.
+``w4`` and ``w4_hat`` evaluate the polynomials of Eq. chebyshev_4th_kind
+through the three-term recurrence that follows it; ``t1_hat`` evaluates
+Eq. chebyshev_1st_kind with NumPy's Chebyshev series. They serve the pins in
+the tests, together with ``poly_spectral`` (the smoother written as the
+polynomial of MA it applies).
 """
 from __future__ import annotations
 
@@ -82,5 +87,68 @@ def cheb4_spectral(gmat: np.ndarray, amat: np.ndarray, b, x0, beta: float, k: in
     bmat = 0.5 * (bmat + bmat.T)
     lam, v = np.linalg.eigh(bmat)
     q = (1.0 - w4_hat(k, lam, beta)) / lam
+    r0 = b - amat @ x0
+    return x0 + gmat.T @ (v @ (q * (v.T @ (gmat @ r0))))
+
+
+def cheb1(apply_a, apply_m, b, x0, alpha: float, beta: float, k: int, x_is_zero: bool = False):
+    """Algorithm 2 (Chebyshev iteration of the first kind, degree k >= 1) with
+    the preconditioner M applied to every residual, on [alpha, beta].
+
+    As a smoother (Sec. 3.2) [alpha, beta] covers only the upper part of the
+    spectrum of MA: alpha = rho lambda_max, rho in (0, 1)."""
+    if k < 1:
+        raise ValueError("degree must be >= 1")
+    if not 0 < alpha < beta:
+        raise ValueError("need 0 < alpha < beta")
+    c = 0.5 * (alpha + beta)
+    d = 0.5 * (beta - alpha)
+    x = np.zeros_like(b) if x_is_zero else np.array(x0, dtype=np.float64, copy=True)
+    r = b.copy() if x_is_zero else b - apply_a(x)
+    p = apply_m(r)
+    omega = 1.0 / c
+    psi = 0.5 * (d * omega) ** 2
+    x = x + omega * p
+    for _ in range(2, k + 1):
+        r = b - apply_a(x)
+        p = apply_m(r) + psi * p
+        omega = 1.0 / (c - psi / omega)
+        psi = (d * omega / 2.0) ** 2
+        x = x + omega * p
+    return x
+
+
+def richardson(apply_a, apply_m, b, x0, omega: float, k: int, x_is_zero: bool = False):
+    """Richardson smoothing: k steps x <- x + omega M (b - A x), i.e.
+    S = (I - omega M A)^k (Sec. 3.2 takes omega = 1)."""
+    if k < 1:
+        raise ValueError("degree must be >= 1")
+    x = np.zeros_like(b) if x_is_zero else np.array(x0, dtype=np.float64, copy=True)
+    for i in range(k):
+        r = b.copy() if (x_is_zero and i == 0) else b - apply_a(x)
+        x = x + omega * apply_m(r)
+    return x
+
+
+def t1_hat(k: int, lam, alpha: float, beta: float):
+    """T^_k(lambda) = T_k((2 lambda - alpha - beta)/(beta - alpha)) /
+    T_k((alpha + beta)/(alpha - beta)) (Eq. chebyshev_1st_kind), with T_k
+    evaluated by numpy.polynomial.chebyshev (not by Algorithm 2's recurrence)."""
+    from numpy.polynomial import chebyshev as npc
+    coef = np.zeros(k + 1)
+    coef[k] = 1.0
+    lam = np.asarray(lam, dtype=np.float64)
+    return npc.chebval((2.0 * lam - alpha - beta) / (beta - alpha), coef) / npc.chebval(
+        (alpha + beta) / (alpha - beta), coef)
+
+
+def poly_spectral(gmat: np.ndarray, amat: np.ndarray, b, x0, pfun):
+    """x_k = x0 + G^T V diag((1 - p(lambda)) / lambda) V^T G r_0 for the
+    residual polynomial p of the smoother (p(0) = 1), G A G^T = V Lambda V^T:
+    the plain definition of any polynomial smoother with M = G^T G."""
+    bmat = gmat @ amat @ gmat.T
+    bmat = 0.5 * (bmat + bmat.T)
+    lam, v = np.linalg.eigh(bmat)
+    q = (1.0 - pfun(lam)) / lam
     r0 = b - amat @ x0
     return x0 + gmat.T @ (v @ (q * (v.T @ (gmat @ r0))))

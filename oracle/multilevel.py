@@ -70,30 +70,51 @@ def coarse_factor(a: Bsr):
     return sla.cho_factor(a.dense(), lower=True)
 
 
-def vcycle(levels: list[Level], l: int, b, k: int):
+def smooth(lev: Level, b, x, degree: int, smoother: str = "cheb4", param: float = 0.0, x_is_zero=False):
+    """One smoother application on a level: "cheb4" (Algorithm 3 on
+    [0, beta]), "cheb1" (Algorithm 2 on [param * beta, beta]) or
+    "richardson" (omega = param)."""
+    if smoother == "cheb4":
+        return chebyshev.cheb4(lev.apply_a, lev.apply_m, b, x, lev.beta, degree, x_is_zero=x_is_zero)
+    if smoother == "cheb1":
+        return chebyshev.cheb1(lev.apply_a, lev.apply_m, b, x, param * lev.beta, lev.beta, degree,
+                               x_is_zero=x_is_zero)
+    if smoother == "richardson":
+        return chebyshev.richardson(lev.apply_a, lev.apply_m, b, x, param, degree, x_is_zero=x_is_zero)
+    raise ValueError(smoother)
+
+
+def vcycle(levels: list[Level], l: int, b, k: int, smoother: str = "cheb4", param: float = 0.0,
+           cycle: str = "vkk"):
     """V(k,k) with zero initial guess: pre-smooth, residual, restrict,
-    recurse, prolongate, post-smooth; exact solve on the coarsest level."""
+    recurse, prolongate, post-smooth; exact solve on the coarsest level.
+    cycle="v2k0": Sec. 5's non-symmetric V(2k,0), one pre-smoothing
+    application of degree 2k and no post-smoothing."""
     lev = levels[l]
     if l == len(levels) - 1:
         return sla.cho_solve(lev.chol, b)
-    x = chebyshev.cheb4(lev.apply_a, lev.apply_m, b, None, lev.beta, k, x_is_zero=True)
+    pre = 2 * k if cycle == "v2k0" else k
+    x = smooth(lev, b, None, pre, smoother, param, x_is_zero=True)
     r = b - lev.apply_a(x)
-    xc = vcycle(levels, l + 1, lev.pb.T @ r, k)
+    xc = vcycle(levels, l + 1, lev.pb.T @ r, k, smoother, param, cycle)
     x = x + lev.pb @ xc
-    x = chebyshev.cheb4(lev.apply_a, lev.apply_m, b, x, lev.beta, k)
-    return x
+    if cycle == "v2k0":
+        return x
+    return smooth(lev, b, x, k, smoother, param)
 
 
-def vcycle_x(levels: list[Level], b, x, k: int):
-    """One V(k,k) cycle from a given initial guess x on level 0."""
+def vcycle_x(levels: list[Level], b, x, k: int, smoother: str = "cheb4", param: float = 0.0, cycle: str = "vkk"):
+    """One cycle from a given initial guess x on level 0."""
     lev = levels[0]
     if len(levels) == 1:
         return sla.cho_solve(lev.chol, b)
-    x = chebyshev.cheb4(lev.apply_a, lev.apply_m, b, x, lev.beta, k)
+    x = smooth(lev, b, x, 2 * k if cycle == "v2k0" else k, smoother, param)
     r = b - lev.apply_a(x)
-    xc = vcycle(levels, 1, lev.pb.T @ r, k)
+    xc = vcycle(levels, 1, lev.pb.T @ r, k, smoother, param, cycle)
     x = x + lev.pb @ xc
-    return chebyshev.cheb4(lev.apply_a, lev.apply_m, b, x, lev.beta, k)
+    if cycle == "v2k0":
+        return x
+    return smooth(lev, b, x, k, smoother, param)
 
 
 def pcg(apply_a, apply_prec, b, rtol: float, maxit: int, flexible: bool = False):
@@ -131,7 +152,8 @@ def pcg(apply_a, apply_prec, b, rtol: float, maxit: int, flexible: bool = False)
     return x, it, hist, true_res
 
 
-def energy_factor(levels: list[Level], e0, k: int, tol: float = 1e-8, maxit: int = 50):
+def energy_factor(levels: list[Level], e0, k: int, tol: float = 1e-8, maxit: int = 50, smoother: str = "cheb4",
+                  param: float = 0.0, cycle: str = "vkk"):
     """Convergence factor in the energy norm (Example 5.1's protocol with b = 0):
     iterate e <- V(0, e) until ||e||_A < tol ||e0||_A or maxit cycles, and
     return (||e_n||_A^2 / ||e_0||_A^2)^{1/(2n)} and n."""
@@ -142,7 +164,7 @@ def energy_factor(levels: list[Level], e0, k: int, tol: float = 1e-8, maxit: int
     n = 0
     en = en0
     while n < maxit:
-        e = vcycle_x(levels, zero, e, k)
+        e = vcycle_x(levels, zero, e, k, smoother, param, cycle)
         n += 1
         en = float(e @ a0.apply_a(e))
         if np.sqrt(en / en0) < tol:

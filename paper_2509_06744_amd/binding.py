@@ -7,19 +7,22 @@ import os
 import numpy as np
 
 __all__ = [
-    "F64", "F32", "BF16", "ChfError", "lib", "lib_path", "version", "current_stream",
+    "F64", "F32", "BF16", "SMOOTH_CHEB4", "SMOOTH_CHEB1", "SMOOTH_RICHARDSON", "CYCLE_VKK", "CYCLE_V2K0",
+    "ChfError", "lib", "lib_path", "version", "current_stream",
     "Bsr", "Pattern", "Fsai", "Levels", "Mlp", "LevelOpts",
     "bsr_create", "bsr_export", "bsr_spmv",
     "pattern_lower", "pattern_from_csr", "pattern_adaptive", "pattern_export",
-    "fsai_setup", "fsai_export", "fsai_apply", "lmax_lanczos", "cheb4_smooth",
+    "fsai_setup", "fsai_export", "fsai_apply", "lmax_lanczos", "cheb4_smooth", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
-    "levels_set_beta", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
+    "levels_set_beta", "levels_set_cycle", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
     "mlp_candidates", "mlp_features", "mlp_create", "mlp_get_params", "mlp_forward",
     "mlp_loss_grad", "mlp_train_step", "mlp_propose", "mlp_labels", "mlp_train",
     "EXPORTED",
 ]
 
 F64, F32, BF16 = 0, 1, 2
+SMOOTH_CHEB4, SMOOTH_CHEB1, SMOOTH_RICHARDSON = 0, 1, 2
+CYCLE_VKK, CYCLE_V2K0 = 0, 1
 CHF_ENOCONV = -5
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -56,6 +59,9 @@ EXPORTED = {
     "chf_fsai_apply": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "chf_lmax_lanczos": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp, _dbl, _pd, _pd, _vp]),
     "chf_cheb4_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
+    "chf_cheb1_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
+    "chf_richardson_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
+    "chf_levels_set_cycle": (C.c_int, [_vp, C.c_int, _dbl, C.c_int]),
     "chf_levels_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "chf_levels_add_coarse": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "chf_levels_setup": (C.c_int, [_vp, C.POINTER(LevelOpts), C.POINTER(_vp), _pi64]),
@@ -282,6 +288,16 @@ def cheb4_smooth(A: Bsr, G: Fsai, beta, degree, b, x, x_is_zero=False, work=None
                                    int(bool(x_is_zero)), _ptr(work), _stream(stream)))
 
 
+def cheb1_smooth(A: Bsr, G: Fsai, alpha, beta, degree, b, x, x_is_zero=False, work=None, dtype=F64, stream=None):
+    _check(_fn("chf_cheb1_smooth")(A.h, G.h, dtype, float(alpha), float(beta), int(degree), _ptr(b), _ptr(x),
+                                   int(bool(x_is_zero)), _ptr(work), _stream(stream)))
+
+
+def richardson_smooth(A: Bsr, G: Fsai, omega, degree, b, x, x_is_zero=False, work=None, dtype=F64, stream=None):
+    _check(_fn("chf_richardson_smooth")(A.h, G.h, dtype, float(omega), int(degree), _ptr(b), _ptr(x),
+                                        int(bool(x_is_zero)), _ptr(work), _stream(stream)))
+
+
 # ----------------------------------------------------------------- levels --
 def levels_create(A0: Bsr) -> Levels:
     out = C.c_void_p()
@@ -344,6 +360,10 @@ def levels_get_beta(L: Levels, level: int) -> float:
 
 def levels_set_beta(L: Levels, level: int, beta: float):
     _check(_fn("chf_levels_set_beta")(L.h, int(level), float(beta)))
+
+
+def levels_set_cycle(L: Levels, smoother=SMOOTH_CHEB4, param=0.0, cycle=CYCLE_VKK):
+    _check(_fn("chf_levels_set_cycle")(L.h, int(smoother), float(param), int(cycle)))
 
 
 def vcycle(L: Levels, b, x, x_is_zero=True, stream=None):

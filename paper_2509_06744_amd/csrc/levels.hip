@@ -12,6 +12,10 @@ namespace chf {
 
 void cheb4_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double beta, int degree,
                 const void* b, void* x, bool x_is_zero, void* work, hipStream_t s);
+void cheb1_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double alpha, double beta, int degree,
+                const void* b, void* x, bool x_is_zero, void* work, hipStream_t s);
+void richardson_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double omega, int degree,
+                     const void* b, void* x, bool x_is_zero, void* work, hipStream_t s);
 chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store, int64_t* bad_row,
                             hipStream_t s);
 void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const double* v0, double safety,
@@ -365,6 +369,9 @@ struct chf_levels_s {
     chf_level_opts opts{};
     bool ready = false;
     chf_dtype vec = CHF_F64;
+    int smoother = CHF_SMOOTH_CHEB4;   // smoother of every level but the coarsest
+    double sm_param = 0.0;             // rho (first kind: alpha_l = rho beta_l) or omega (Richardson)
+    int cycle = CHF_CYCLE_VKK;
     DevBuf<double> pcg_buf, scal, part;
     int64_t pcg_n = 0;
     ~chf_levels_s() {
@@ -446,7 +453,28 @@ static void prolong_add(chf_levels_s& H, int l, const void* xc, void* x, hipStre
     CHF_LAUNCH_CHECK();
 }
 
-// V(k,k) on level l: pre-smooth, residual, restrict, recurse, prolongate, post-smooth.
+// One smoother application of the given degree on level l.
+static void smooth_level(chf_levels_s& H, int l, int degree, const void* b, void* x, bool x_is_zero, hipStream_t s) {
+    chf_level_s& L = H.lev[l];
+    const Sell& A = level_A(H, l, s);
+    const chf_dtype gdt = H.vec == CHF_F64 ? CHF_F64 : L.G->store;
+    const Sell& G = L.G->g(gdt);
+    const Sell& Gt = L.G->gt(gdt);
+    switch (H.smoother) {
+        case CHF_SMOOTH_CHEB1:
+            cheb1_impl(A, G, Gt, H.vec, H.sm_param * L.beta, L.beta, degree, b, x, x_is_zero, L.work.p, s);
+            break;
+        case CHF_SMOOTH_RICHARDSON:
+            richardson_impl(A, G, Gt, H.vec, H.sm_param, degree, b, x, x_is_zero, L.work.p, s);
+            break;
+        default:
+            cheb4_impl(A, G, Gt, H.vec, L.beta, degree, b, x, x_is_zero, L.work.p, s);
+    }
+}
+
+// V(k,k) on level l: pre-smooth, residual, restrict, recurse, prolongate,
+// post-smooth. V(2k,0): one pre-smoothing application of degree 2k and no
+// post-smoothing (the non-symmetric cycle of Sec. 5).
 static void vcycle_rec(chf_levels_s& H, int l, const void* b, void* x, bool x_is_zero, hipStream_t s) {
     const int nl = (int)H.lev.size();
     chf_level_s& L = H.lev[l];
@@ -455,15 +483,15 @@ static void vcycle_rec(chf_levels_s& H, int l, const void* b, void* x, bool x_is
         return;
     }
     const Sell& A = level_A(H, l, s);
-    chf_dtype gdt = H.vec == CHF_F64 ? CHF_F64 : L.G->store;
     const int k = H.opts.degree;
-    cheb4_impl(A, L.G->g(gdt), L.G->gt(gdt), H.vec, L.beta, k, b, x, x_is_zero, L.work.p, s);
+    const bool v2k0 = H.cycle == CHF_CYCLE_V2K0;
+    smooth_level(H, l, v2k0 ? 2 * k : k, b, x, x_is_zero, s);
     sell_spmv(A, H.vec, x, L.rvec.p, b, EPI_RES, nullptr, nullptr, 0, 0, s);
     chf_level_s& C = H.lev[l + 1];
     restrict_to(H, l, L.rvec.p, C.bvec.p, s);
     vcycle_rec(H, l + 1, C.bvec.p, C.xvec.p, true, s);
     prolong_add(H, l, C.xvec.p, x, s);
-    cheb4_impl(A, L.G->g(gdt), L.G->gt(gdt), H.vec, L.beta, k, b, x, false, L.work.p, s);
+    if (!v2k0) smooth_level(H, l, k, b, x, false, s);
 }
 
 static void build_coarse_dense(chf_level_s& L, hipStream_t s) {
@@ -749,12 +777,30 @@ extern "C" int chf_vcycle(chf_levels H, const void* b, void* x, int x_is_zero, h
     });
 }
 
+extern "C" int chf_levels_set_cycle(chf_levels H, chf_smoother smoother, double param, chf_cycle cycle) {
+    return guarded([&] {
+        CHF_CHECK(H, CHF_EINVAL, "NULL hierarchy");
+        CHF_CHECK(smoother == CHF_SMOOTH_CHEB4 || smoother == CHF_SMOOTH_CHEB1 || smoother == CHF_SMOOTH_RICHARDSON,
+                  CHF_EINVAL, "unknown smoother");
+        CHF_CHECK(cycle == CHF_CYCLE_VKK || cycle == CHF_CYCLE_V2K0, CHF_EINVAL, "unknown cycle");
+        if (smoother == CHF_SMOOTH_CHEB1)
+            CHF_CHECK(param > 0.0 && param < 1.0, CHF_EINVAL, "first-kind smoothing needs 0 < rho < 1");
+        if (smoother == CHF_SMOOTH_RICHARDSON)
+            CHF_CHECK(param > 0.0 && std::isfinite(param), CHF_EINVAL, "Richardson needs omega > 0");
+        H->smoother = smoother;
+        H->sm_param = param;
+        H->cycle = cycle;
+    });
+}
+
 extern "C" int chf_pcg_solve(chf_levels H, const double* b, double* x, double rtol, int maxit, int flexible,
                              int* iters, double* relres_hist, double* true_relres, hipStream_t stream) {
     int status = CHF_OK;
     int rc = guarded([&] {
         check_ready(H);
         CHF_CHECK(b && x && maxit >= 0 && rtol >= 0, CHF_EINVAL, "bad argument");
+        CHF_CHECK(flexible || H->cycle == CHF_CYCLE_VKK, CHF_EINVAL,
+                  "a V(2k,0) cycle is not symmetric: use the flexible form");
         hipStream_t s = stream;
         chf_level_s& L0 = H->lev[0];
         const int64_t n = L0.A->nb * (int64_t)L0.A->b;

@@ -1,51 +1,127 @@
-// Fourth-kind Chebyshev smoothing (Algorithm 3) with M = G^T G.
+// Polynomial smoothers with M = G^T G, all written as the same two-term step
+//   r = b - A x,  p = a_i p + M r,  x += c_i p        (step 1: p = M r)
+// with per-step scalars formed on the host, so nothing is read back:
+//   - Algorithm 3 (Chebyshev iteration of the fourth kind) on [0, beta];
+//   - Algorithm 2 (Chebyshev iteration of the first kind), preconditioned,
+//     on a smoothing interval [alpha, beta] (Sec. 3.2);
+//   - Richardson smoothing S = (I - omega M A)^k (Sec. 3.2, omega = 1 there).
 //
 // Each step is three kernels: r = b - A x (skipped in the first step when x
-// starts at zero), t = G r, and z = G^T t fused with the recurrence
-// p = mu^2 p + z; mu <- 1 / (2 - mu); x += d mu p (first step: p = z). The
-// scalars mu_i and d mu_i are formed on the host, so nothing is read back.
+// starts at zero), t = G r, and z = G^T t fused with the update of p and x.
 #include <cmath>
+#include <vector>
 
 #include "internal.h"
 
 namespace chf {
 
-void cheb4_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double beta, int degree,
-                const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
-    CHF_CHECK(degree >= 1, CHF_EINVAL, "degree must be >= 1");
-    CHF_CHECK(beta > 0 && std::isfinite(beta), CHF_EINVAL, "beta must be positive and finite");
+struct StepCoef {
+    std::vector<double> a;   // a[i]: weight of the previous p in step i (a[0] unused)
+    std::vector<double> c;   // c[i]: x += c[i] p
+};
+
+// Algorithm 3: mu_1 = 1/3, p_i = mu_{i-1}^2 p_{i-1} + M r_i, mu_i = 1/(2 - mu_{i-1}),
+// x += (4 / beta) mu_i p_i.
+static StepCoef cheb4_coef(double beta, int k) {
+    StepCoef s;
+    const double d = 4.0 / beta;
+    double mu = 1.0 / 3.0;
+    s.a.push_back(0.0);
+    s.c.push_back(d * mu);
+    for (int i = 2; i <= k; ++i) {
+        const double alpha = mu * mu;
+        mu = 1.0 / (2.0 - mu);
+        s.a.push_back(alpha);
+        s.c.push_back(d * mu);
+    }
+    return s;
+}
+
+// Algorithm 2 with the preconditioner: c = (alpha + beta) / 2,
+// d = (beta - alpha) / 2, omega_1 = 1 / c, psi_1 = (d omega_1)^2 / 2; then
+// p_i = M r_i + psi_{i-1} p_{i-1}, omega_i = 1 / (c - psi_{i-1} / omega_{i-1}),
+// psi_i = (d omega_i / 2)^2, x += omega_i p_i.
+static StepCoef cheb1_coef(double alpha, double beta, int k) {
+    StepCoef s;
+    const double c = 0.5 * (alpha + beta), d = 0.5 * (beta - alpha);
+    double omega = 1.0 / c;
+    double psi = 0.5 * (d * omega) * (d * omega);
+    s.a.push_back(0.0);
+    s.c.push_back(omega);
+    for (int i = 2; i <= k; ++i) {
+        s.a.push_back(psi);
+        omega = 1.0 / (c - psi / omega);
+        psi = (0.5 * d * omega) * (0.5 * d * omega);
+        s.c.push_back(omega);
+    }
+    return s;
+}
+
+static StepCoef richardson_coef(double omega, int k) {
+    StepCoef s;
+    for (int i = 1; i <= k; ++i) {
+        s.a.push_back(0.0);
+        s.c.push_back(omega);
+    }
+    return s;
+}
+
+static void poly_smooth_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, const StepCoef& cf,
+                             const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
+    const int k = (int)cf.c.size();
     const int64_t n = A.nb * (int64_t)A.b;
     const size_t es = vec_size(vec);
     char* w = static_cast<char*>(work);
     void* r = w;
     void* t = w + n * es;
     void* p = w + 2 * n * es;
-    const double d = 4.0 / beta;
-    double mu = 1.0 / 3.0;
-    // step 1: r = b - A x0 (or b), p = M r, x = x0 + d mu p
+    // step 1: r = b - A x0 (or b), p = M r, x = x0 + c_1 p
     const void* r0 = b;
     if (!x_is_zero) {
         sell_spmv(A, vec, x, r, b, EPI_RES, nullptr, nullptr, 0, 0, s);
         r0 = r;
     }
     sell_spmv(G, vec, r0, t, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
-    sell_spmv(Gt, vec, t, nullptr, nullptr, x_is_zero ? EPI_CHEB_FIRST0 : EPI_CHEB_FIRST, p, x, 0.0, d * mu, s);
-    for (int i = 2; i <= degree; ++i) {
-        // r = b - A x ; p = mu^2 p + M r ; mu = 1/(2 - mu) ; x += d mu p
+    sell_spmv(Gt, vec, t, nullptr, nullptr, x_is_zero ? EPI_CHEB_FIRST0 : EPI_CHEB_FIRST, p, x, 0.0, cf.c[0], s);
+    for (int i = 1; i < k; ++i) {
         sell_spmv(A, vec, x, r, b, EPI_RES, nullptr, nullptr, 0, 0, s);
         sell_spmv(G, vec, r, t, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
-        const double alpha = mu * mu;
-        mu = 1.0 / (2.0 - mu);
-        sell_spmv(Gt, vec, t, nullptr, nullptr, EPI_CHEB, p, x, alpha, d * mu, s);
+        sell_spmv(Gt, vec, t, nullptr, nullptr, EPI_CHEB, p, x, cf.a[i], cf.c[i], s);
     }
+}
+
+static void check_degree(int degree) { CHF_CHECK(degree >= 1, CHF_EINVAL, "degree must be >= 1"); }
+
+void cheb4_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double beta, int degree,
+                const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
+    check_degree(degree);
+    CHF_CHECK(beta > 0 && std::isfinite(beta), CHF_EINVAL, "beta must be positive and finite");
+    poly_smooth_impl(A, G, Gt, vec, cheb4_coef(beta, degree), b, x, x_is_zero, work, s);
+}
+
+void cheb1_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double alpha, double beta, int degree,
+                const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
+    check_degree(degree);
+    CHF_CHECK(alpha > 0 && beta > alpha && std::isfinite(beta), CHF_EINVAL, "need 0 < alpha < beta < inf");
+    poly_smooth_impl(A, G, Gt, vec, cheb1_coef(alpha, beta, degree), b, x, x_is_zero, work, s);
+}
+
+void richardson_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double omega, int degree,
+                     const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
+    check_degree(degree);
+    CHF_CHECK(omega > 0 && std::isfinite(omega), CHF_EINVAL, "omega must be positive and finite");
+    poly_smooth_impl(A, G, Gt, vec, richardson_coef(omega, degree), b, x, x_is_zero, work, s);
 }
 
 }  // namespace chf
 
 using namespace chf;
 
-extern "C" int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree, const void* b,
-                                void* x, int x_is_zero, void* work, hipStream_t stream) {
+namespace {
+// resolve the operand layouts for a smoother call on (A, G) in `dtype`
+template <class F>
+int with_operands(chf_bsr A, chf_fsai G, chf_dtype dtype, const void* b, void* x, void* work, hipStream_t stream,
+                  F&& f) {
     return guarded([&] {
         CHF_CHECK(A && G && b && x && work, CHF_EINVAL, "NULL argument");
         CHF_CHECK(A->nb == G->nb && A->b == G->b, CHF_EINVAL, "A and G sizes differ");
@@ -53,6 +129,28 @@ extern "C" int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double b
                   "dtype must be F64 or the factor's storage dtype");
         chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
         const Sell& sa = A->sell(vec, stream);
-        cheb4_impl(sa, G->g(dtype), G->gt(dtype), vec, beta, degree, b, x, x_is_zero != 0, work, stream);
+        f(sa, G->g(dtype), G->gt(dtype), vec);
+    });
+}
+}  // namespace
+
+extern "C" int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree, const void* b,
+                                void* x, int x_is_zero, void* work, hipStream_t stream) {
+    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const Sell& g, const Sell& gt, chf_dtype vec) {
+        cheb4_impl(sa, g, gt, vec, beta, degree, b, x, x_is_zero != 0, work, stream);
+    });
+}
+
+extern "C" int chf_cheb1_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double alpha, double beta, int degree,
+                                const void* b, void* x, int x_is_zero, void* work, hipStream_t stream) {
+    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const Sell& g, const Sell& gt, chf_dtype vec) {
+        cheb1_impl(sa, g, gt, vec, alpha, beta, degree, b, x, x_is_zero != 0, work, stream);
+    });
+}
+
+extern "C" int chf_richardson_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double omega, int degree,
+                                     const void* b, void* x, int x_is_zero, void* work, hipStream_t stream) {
+    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const Sell& g, const Sell& gt, chf_dtype vec) {
+        richardson_impl(sa, g, gt, vec, omega, degree, b, x, x_is_zero != 0, work, stream);
     });
 }
