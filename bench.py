@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-setup3d", action="store_true")
     ap.add_argument("--setup3d-grid", type=int, default=64, help="3D patch grid of the batched set-up leg")
     ap.add_argument("--setup3d-tmax", type=int, default=23)
@@ -155,6 +156,46 @@ def setup3d_leg(args, chf, torch):
            "note": "fsai_setup_ms is the whole call: local factorisations, G^T transpose map, SpMV layouts"}
     log(f"3D batched set-up: {rec}")
     return rec
+
+
+def comparators_leg(args, chf, torch, dev, H, A, bd, N, k):
+    """The smoothers and cycles that Sec. 3.2 and Sec. 5 compare, on the same
+    FP64 hierarchy (same patterns, factors and bounds beta_l): fourth-kind
+    Chebyshev, first-kind Chebyshev on [0.3 beta, beta], Richardson
+    (omega = 1, S = (I - MA)^k), each in V(k,k), and fourth-kind Chebyshev in
+    V(2k,0). For each: the energy-norm convergence factor of the cycle from a
+    U(-1,1) error, and PCG to 1e-8 (CG for the symmetric cycles, flexible CG
+    for V(2k,0))."""
+    from paper_2509_06744_amd import learned
+    from problems import uniform_start
+    e0 = torch.from_numpy(uniform_start(0, N)).to(dev)
+    runs = [("cheb4_Vkk", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_VKK),
+            ("cheb1_rho0.3_Vkk", chf.SMOOTH_CHEB1, 0.3, chf.CYCLE_VKK),
+            ("richardson_omega1_Vkk", chf.SMOOTH_RICHARDSON, 1.0, chf.CYCLE_VKK),
+            ("cheb4_V2k0", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_V2K0)]
+    out = {}
+    for name, sm, par, cyc in runs:
+        chf.levels_set_cycle(H, sm, par, cyc)
+        rec = {}
+        rho, ncyc = learned.energy_factor(H, A, e0, maxit=30)
+        rec["rho_A"], rec["cycles"] = round(rho, 5), ncyc
+        flex = cyc == chf.CYCLE_V2K0
+        xs = torch.zeros(N, dtype=torch.float64, device=dev)
+        try:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            it, hist, tr, rc = chf.pcg_solve(H, bd, xs, rtol=1e-8, maxit=200, flexible=flex, raise_on_noconv=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            rec.update({"pcg_iterations": it, "pcg_time_ms": round(1e3 * el, 2),
+                        "ms_per_iteration": round(1e3 * el / max(it, 1), 3), "converged": rc == 0,
+                        "true_relres": tr, "flexible_cg": flex})
+        except chf.ChfError as e:
+            rec["pcg_error"] = str(e)
+        out[name] = rec
+        log(f"comparator {name}: {rec}")
+    chf.levels_set_cycle(H, chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_VKK)
+    return out
 
 
 def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
@@ -410,6 +451,8 @@ def main():
         res["mixed_bf16g_over_fp64_time"] = round(res["mixed_bf16g"]["time_ms"] / res["fp64"]["time_ms"], 4)
         out["pcg"] = res
 
+    if not args.no_comparators:
+        out["comparators"] = comparators_leg(args, chf, torch, dev, H, A, bd, N, k)
     if not args.no_learned:
         out["learned"] = learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases)
     if not args.no_setup3d:
