@@ -164,32 +164,42 @@ def comparators_leg(args, chf, torch, dev, H, A, bd, N, k):
     Chebyshev, first-kind Chebyshev on [0.3 beta, beta], Richardson
     (omega = 1, S = (I - MA)^k), each in V(k,k), and fourth-kind Chebyshev in
     V(2k,0). For each: the energy-norm convergence factor of the cycle from a
-    U(-1,1) error, and PCG to 1e-8 (CG for the symmetric cycles, flexible CG
-    for V(2k,0))."""
+    U(-1,1) error, and a Krylov solve to 1e-8: CG for the symmetric cycles,
+    flexible CG and BiCGStab (two cycles per iteration) for V(2k,0), and
+    BiCGStab with V(k,k) for reference."""
     from paper_2509_06744_amd import learned
     from problems import uniform_start
     e0 = torch.from_numpy(uniform_start(0, N)).to(dev)
     runs = [("cheb4_Vkk", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_VKK),
             ("cheb1_rho0.3_Vkk", chf.SMOOTH_CHEB1, 0.3, chf.CYCLE_VKK),
             ("richardson_omega1_Vkk", chf.SMOOTH_RICHARDSON, 1.0, chf.CYCLE_VKK),
-            ("cheb4_V2k0", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_V2K0)]
+            ("cheb4_V2k0", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_V2K0),
+            ("cheb4_V2k0_bicgstab", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_V2K0),
+            ("cheb4_Vkk_bicgstab", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_VKK)]
     out = {}
     for name, sm, par, cyc in runs:
         chf.levels_set_cycle(H, sm, par, cyc)
         rec = {}
-        rho, ncyc = learned.energy_factor(H, A, e0, maxit=30)
-        rec["rho_A"], rec["cycles"] = round(rho, 5), ncyc
+        bicg = name.endswith("_bicgstab")
+        if not bicg:
+            rho, ncyc = learned.energy_factor(H, A, e0, maxit=30)
+            rec["rho_A"], rec["cycles"] = round(rho, 5), ncyc
         flex = cyc == chf.CYCLE_V2K0
         xs = torch.zeros(N, dtype=torch.float64, device=dev)
         try:
             torch.cuda.synchronize()
             t = time.perf_counter()
-            it, hist, tr, rc = chf.pcg_solve(H, bd, xs, rtol=1e-8, maxit=200, flexible=flex, raise_on_noconv=False)
+            if bicg:
+                it, hist, tr, rc = chf.bicgstab_solve(H, bd, xs, rtol=1e-8, maxit=200, raise_on_noconv=False)
+            else:
+                it, hist, tr, rc = chf.pcg_solve(H, bd, xs, rtol=1e-8, maxit=200, flexible=flex,
+                                                 raise_on_noconv=False)
             torch.cuda.synchronize()
             el = time.perf_counter() - t
-            rec.update({"pcg_iterations": it, "pcg_time_ms": round(1e3 * el, 2),
+            rec.update({"solver": "bicgstab" if bicg else ("flexible_cg" if flex else "cg"),
+                        "iterations": it, "time_ms": round(1e3 * el, 2),
                         "ms_per_iteration": round(1e3 * el / max(it, 1), 3), "converged": rc == 0,
-                        "true_relres": tr, "flexible_cg": flex})
+                        "true_relres": tr, "preconditioner_applications": (2 * it if bicg else it)})
         except chf.ChfError as e:
             rec["pcg_error"] = str(e)
         out[name] = rec

@@ -194,6 +194,15 @@ int chf_vcycle(chf_levels L, const void* b, void* x, int x_is_zero, hipStream_t 
 int chf_pcg_solve(chf_levels L, const double* b, double* x, double rtol, int maxit,
                   int flexible, int* iters, double* relres_hist, double* true_relres,
                   hipStream_t stream);
+/* Right-preconditioned BiCGStab (van der Vorst 1992) from x = 0 with one
+ * cycle as preconditioner: the outer solver Sec. 6 names for the
+ * non-symmetric V(2k,0) cycle (any cycle is accepted). Shadow residual b.
+ * Stops when ||r|| <= rtol ||b||, checked at both half steps of an iteration.
+ * relres_hist (host, 2*maxit+1, may be NULL) receives the residual norm
+ * after every half step; true_relres as for chf_pcg_solve. EBREAKDOWN if
+ * (r^, r), (r^, v) or omega vanish; ENOCONV if maxit is reached. */
+int chf_bicgstab_solve(chf_levels L, const double* b, double* x, double rtol, int maxit,
+                       int* iters, double* relres_hist, double* true_relres, hipStream_t stream);
 
 /* ------------------------------------------------------- learned pattern -- */
 /* Not part of the paper: a small network, trained on patterns that Algorithm 1

@@ -152,6 +152,52 @@ def pcg(apply_a, apply_prec, b, rtol: float, maxit: int, flexible: bool = False)
     return x, it, hist, true_res
 
 
+def bicgstab(apply_a, apply_prec, b, rtol: float, maxit: int):
+    """Right-preconditioned BiCGStab (van der Vorst, 1992) from x0 = 0 with
+    shadow residual r^ = b: the outer solver that accepts the non-symmetric
+    V(2k,0) preconditioner (Sec. 6). Stops when the recursive residual
+    (also checked at the half step s) satisfies ||r|| <= rtol ||b||. Returns
+    (x, iterations, residual history per half step, true relative residual)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    rhat = b.copy()
+    bnorm = float(np.linalg.norm(b))
+    hist = [float(np.linalg.norm(r)) / bnorm]
+    if hist[0] <= rtol:
+        return x, 0, hist, hist[0]
+    p = np.zeros_like(b)
+    v = np.zeros_like(b)
+    rho_old = alpha = omega = 1.0
+    it = 0
+    for it in range(1, maxit + 1):
+        rho = float(rhat @ r)
+        if rho == 0.0:
+            raise ArithmeticError("BiCGStab breakdown: (r^, r) = 0")
+        if it == 1:
+            p = r.copy()
+        else:
+            p = r + (rho / rho_old) * (alpha / omega) * (p - omega * v)
+        ph = apply_prec(p)
+        v = apply_a(ph)
+        alpha = rho / float(rhat @ v)
+        s = r - alpha * v
+        hist.append(float(np.linalg.norm(s)) / bnorm)
+        if hist[-1] <= rtol:
+            x = x + alpha * ph
+            break
+        sh = apply_prec(s)
+        t = apply_a(sh)
+        omega = float(t @ s) / float(t @ t)
+        x = x + alpha * ph + omega * sh
+        r = s - omega * t
+        hist.append(float(np.linalg.norm(r)) / bnorm)
+        if hist[-1] <= rtol:
+            break
+        rho_old = rho
+    true_res = float(np.linalg.norm(b - apply_a(x))) / bnorm
+    return x, it, hist, true_res
+
+
 def energy_factor(levels: list[Level], e0, k: int, tol: float = 1e-8, maxit: int = 50, smoother: str = "cheb4",
                   param: float = 0.0, cycle: str = "vkk"):
     """Convergence factor in the energy norm (Example 5.1's protocol with b = 0):

@@ -15,6 +15,7 @@ __all__ = [
     "fsai_setup", "fsai_export", "fsai_apply", "lmax_lanczos", "cheb4_smooth", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
     "levels_set_beta", "levels_set_cycle", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
+    "bicgstab_solve",
     "mlp_candidates", "mlp_features", "mlp_create", "mlp_get_params", "mlp_forward",
     "mlp_loss_grad", "mlp_train_step", "mlp_propose", "mlp_labels", "mlp_train",
     "EXPORTED",
@@ -62,6 +63,7 @@ EXPORTED = {
     "chf_cheb1_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "chf_richardson_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "chf_levels_set_cycle": (C.c_int, [_vp, C.c_int, _dbl, C.c_int]),
+    "chf_bicgstab_solve": (C.c_int, [_vp, _vp, _vp, _dbl, C.c_int, _pint, _vp, _pd, _vp]),
     "chf_levels_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "chf_levels_add_coarse": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
     "chf_levels_setup": (C.c_int, [_vp, C.POINTER(LevelOpts), C.POINTER(_vp), _pi64]),
@@ -380,6 +382,18 @@ def pcg_solve(L: Levels, b, x, rtol=1e-8, maxit=200, flexible=False, stream=None
     if rc != 0 and not (rc == CHF_ENOCONV and not raise_on_noconv):
         _check(rc)
     return iters.value, hist[:iters.value + 1], tr.value, rc
+
+
+def bicgstab_solve(L: Levels, b, x, rtol=1e-8, maxit=200, stream=None, raise_on_noconv=True):
+    """Returns (iterations, residual history per half step, true relative residual, status)."""
+    iters = C.c_int()
+    hist = np.full(2 * maxit + 1, np.nan, np.float64)
+    tr = C.c_double()
+    rc = _fn("chf_bicgstab_solve")(L.h, _ptr(b), _ptr(x), float(rtol), int(maxit), C.byref(iters),
+                                   hist.ctypes.data_as(C.c_void_p), C.byref(tr), _stream(stream))
+    if rc != 0 and not (rc == CHF_ENOCONV and not raise_on_noconv):
+        _check(rc)
+    return iters.value, hist[~np.isnan(hist)], tr.value, rc
 
 
 # -------------------------------------------------------------------- MLP --

@@ -334,6 +334,47 @@ __global__ void k_copy_scalar(double* __restrict__ scal, int from, int to) {
     if (threadIdx.x == 0 && blockIdx.x == 0) scal[to] = scal[from];
 }
 
+// ---------------------------------------------------------- BiCGStab ops --
+// bs layout (device doubles): 0 rho, 1 rho_old, 2 alpha, 3 omega, 4 (r^, v),
+// 5 (t, s), 6 (t, t), 7 squared norm of the residual checked last
+__global__ void k_bicg_p(int64_t n, const double* __restrict__ bs, const double* __restrict__ r,
+                         const double* __restrict__ v, double* __restrict__ p, int first) {
+    const double beta = first ? 0.0 : (bs[0] / bs[1]) * (bs[2] / bs[3]);
+    const double om = first ? 0.0 : bs[3];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = first ? r[i] : r[i] + beta * (p[i] - om * v[i]);
+}
+
+// alpha = rho / (r^, v); s = r - alpha v
+__global__ void k_bicg_s(int64_t n, double* __restrict__ bs, const double* __restrict__ r,
+                         const double* __restrict__ v, double* __restrict__ s) {
+    const double alpha = bs[0] / bs[4];
+    if (blockIdx.x == 0 && threadIdx.x == 0) bs[2] = alpha;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        s[i] = r[i] - alpha * v[i];
+}
+
+// omega = (t, s) / (t, t); x += alpha p^ + omega s^; r = s - omega t
+__global__ void k_bicg_xr(int64_t n, double* __restrict__ bs, const double* __restrict__ ph,
+                          const double* __restrict__ sh, const double* __restrict__ s, const double* __restrict__ t,
+                          double* __restrict__ x, double* __restrict__ r) {
+    const double alpha = bs[0] / bs[4];
+    const double omega = bs[5] / bs[6];
+    if (blockIdx.x == 0 && threadIdx.x == 0) bs[3] = omega;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += alpha * ph[i] + omega * sh[i];
+        r[i] = s[i] - omega * t[i];
+    }
+}
+
+// x += alpha p^ (convergence at the half step)
+__global__ void k_bicg_half(int64_t n, const double* __restrict__ bs, const double* __restrict__ ph,
+                            double* __restrict__ x) {
+    const double alpha = bs[0] / bs[4];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += alpha * ph[i];
+}
+
 }  // namespace chf
 
 using namespace chf;
@@ -369,6 +410,8 @@ struct chf_levels_s {
     chf_level_opts opts{};
     bool ready = false;
     chf_dtype vec = CHF_F64;
+    DevBuf<double> bicg_buf, bicg_scal;
+    int64_t bicg_n = 0;
     int smoother = CHF_SMOOTH_CHEB4;   // smoother of every level but the coarsest
     double sm_param = 0.0;             // rho (first kind: alpha_l = rho beta_l) or omega (Richardson)
     int cycle = CHF_CYCLE_VKK;
@@ -889,6 +932,132 @@ extern "C" int chf_pcg_solve(chf_levels H, const double* b, double* x, double rt
         if (status == CHF_OK && !converged) {
             status = CHF_ENOCONV;
             set_error("PCG did not reach rtol within maxit iterations");
+        }
+    });
+    return rc != CHF_OK ? rc : status;
+}
+
+extern "C" int chf_bicgstab_solve(chf_levels H, const double* b, double* x, double rtol, int maxit, int* iters,
+                                  double* relres_hist, double* true_relres, hipStream_t stream) {
+    int status = CHF_OK;
+    int rc = guarded([&] {
+        check_ready(H);
+        CHF_CHECK(b && x && maxit >= 0 && rtol >= 0, CHF_EINVAL, "bad argument");
+        hipStream_t s = stream;
+        chf_level_s& L0 = H->lev[0];
+        const int64_t n = L0.A->nb * (int64_t)L0.A->b;
+        if (H->bicg_n != n) {
+            H->bicg_buf.alloc((size_t)std::max<int64_t>(1, 8 * n));
+            H->bicg_scal.alloc(16);
+            H->part.alloc(RED_BLOCKS);
+            H->bicg_n = n;
+        }
+        double* r = H->bicg_buf.p;
+        double* rh = r + n;
+        double* p = rh + n;
+        double* v = p + n;
+        double* ph = v + n;
+        double* sv = ph + n;
+        double* sh = sv + n;
+        double* t = sh + n;
+        double* bs = H->bicg_scal.p;
+        const Sell& A64 = L0.A->sell(CHF_F64, s);
+        const int grid = (int)std::min<int64_t>((n + 255) / 256, 8192);
+        auto precond = [&](const double* rin, double* zout) {
+            if (H->vec == CHF_F64) {
+                vcycle_rec(*H, 0, rin, zout, true, s);
+            } else {
+                cast_vec(CHF_F64, rin, CHF_F32, L0.bvec.p, n, s);
+                vcycle_rec(*H, 0, L0.bvec.p, L0.xvec.p, true, s);
+                cast_vec(CHF_F32, L0.xvec.p, CHF_F64, zout, n, s);
+            }
+        };
+        auto read = [&](int idx) {
+            double val;
+            CHF_HIP(hipMemcpyAsync(&val, bs + idx, 8, hipMemcpyDeviceToHost, s));
+            CHF_HIP(hipStreamSynchronize(s));
+            return val;
+        };
+        fill_zero(x, n * 8, s);
+        cast_vec(CHF_F64, b, CHF_F64, r, n, s);
+        cast_vec(CHF_F64, b, CHF_F64, rh, n, s);
+        dot(CHF_F64, b, b, n, bs + 7, H->part.p, s);
+        const double bnorm = std::sqrt(read(7));
+        CHF_CHECK(std::isfinite(bnorm), CHF_EINVAL, "non-finite right-hand side");
+        int it = 0, nh = 0;
+        if (relres_hist) relres_hist[nh++] = bnorm > 0 ? 1.0 : 0.0;
+        if (bnorm == 0.0 || 1.0 <= rtol) {
+            if (iters) *iters = 0;
+            if (true_relres) *true_relres = 0.0;
+            return;
+        }
+        bool converged = false;
+        for (it = 1; it <= maxit; ++it) {
+            dot(CHF_F64, rh, r, n, bs + 0, H->part.p, s);
+            hipLaunchKernelGGL(k_bicg_p, dim3(grid), dim3(256), 0, s, n, (const double*)bs, (const double*)r,
+                               (const double*)v, p, it == 1 ? 1 : 0);
+            CHF_LAUNCH_CHECK();
+            precond(p, ph);
+            sell_spmv(A64, CHF_F64, ph, v, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+            dot(CHF_F64, rh, v, n, bs + 4, H->part.p, s);
+            hipLaunchKernelGGL(k_bicg_s, dim3(grid), dim3(256), 0, s, n, bs, (const double*)r, (const double*)v, sv);
+            CHF_LAUNCH_CHECK();
+            dot(CHF_F64, sv, sv, n, bs + 7, H->part.p, s);
+            double hs[8];
+            CHF_HIP(hipMemcpyAsync(hs, bs, 64, hipMemcpyDeviceToHost, s));
+            CHF_HIP(hipStreamSynchronize(s));
+            if (hs[0] == 0.0 || hs[4] == 0.0 || !std::isfinite(hs[2])) {
+                status = CHF_EBREAKDOWN;
+                set_error("BiCGStab breakdown: (r^, r) or (r^, v) vanished");
+                break;
+            }
+            double rel = std::sqrt(hs[7]) / bnorm;
+            if (relres_hist) relres_hist[nh++] = rel;
+            if (rel <= rtol) {
+                hipLaunchKernelGGL(k_bicg_half, dim3(grid), dim3(256), 0, s, n, (const double*)bs,
+                                   (const double*)ph, x);
+                CHF_LAUNCH_CHECK();
+                converged = true;
+                break;
+            }
+            precond(sv, sh);
+            sell_spmv(A64, CHF_F64, sh, t, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+            dot(CHF_F64, t, sv, n, bs + 5, H->part.p, s);
+            dot(CHF_F64, t, t, n, bs + 6, H->part.p, s);
+            hipLaunchKernelGGL(k_bicg_xr, dim3(grid), dim3(256), 0, s, n, bs, (const double*)ph, (const double*)sh,
+                               (const double*)sv, (const double*)t, x, r);
+            CHF_LAUNCH_CHECK();
+            dot(CHF_F64, r, r, n, bs + 7, H->part.p, s);
+            CHF_HIP(hipMemcpyAsync(hs, bs, 64, hipMemcpyDeviceToHost, s));
+            CHF_HIP(hipStreamSynchronize(s));
+            if (!(hs[6] > 0.0) || !std::isfinite(hs[3]) || hs[3] == 0.0) {
+                status = CHF_EBREAKDOWN;
+                set_error("BiCGStab breakdown: omega vanished");
+                break;
+            }
+            rel = std::sqrt(hs[7]) / bnorm;
+            if (relres_hist) relres_hist[nh++] = rel;
+            if (!std::isfinite(rel)) {
+                status = CHF_EBREAKDOWN;
+                set_error("BiCGStab produced a non-finite residual");
+                break;
+            }
+            if (rel <= rtol) {
+                converged = true;
+                break;
+            }
+            hipLaunchKernelGGL(k_copy_scalar, dim3(1), dim3(1), 0, s, bs, 0, 1);
+            CHF_LAUNCH_CHECK();
+        }
+        if (iters) *iters = std::min(it, maxit);
+        if (true_relres) {
+            sell_spmv(A64, CHF_F64, x, t, b, EPI_RES, nullptr, nullptr, 0, 0, s);
+            dot(CHF_F64, t, t, n, bs + 7, H->part.p, s);
+            *true_relres = std::sqrt(read(7)) / bnorm;
+        }
+        if (status == CHF_OK && !converged) {
+            status = CHF_ENOCONV;
+            set_error("BiCGStab did not reach rtol within maxit iterations");
         }
     });
     return rc != CHF_OK ? rc : status;

@@ -1,6 +1,7 @@
 """GPU parity of the comparator smoothers of Sec. 3.2 (first-kind Chebyshev,
-Algorithm 2; Richardson smoothing) and of the V(2k,0) cycle of Sec. 5 against
-the oracle, through the C ABI; error paths of the new entry points."""
+Algorithm 2; Richardson smoothing), of the V(2k,0) cycle of Sec. 5 and of
+BiCGStab, its outer solver, against the oracle, through the C ABI; error
+paths of the new entry points."""
 import numpy as np
 import pytest
 
@@ -143,3 +144,36 @@ def test_set_cycle_errors(chf):
         with pytest.raises(chf.ChfError) as ei:
             chf.levels_set_cycle(L, sm, par, cy)
         assert ei.value.code == -1
+
+
+@pytest.mark.parametrize("cycle", ["v2k0", "vkk"])
+def test_bicgstab_matches_oracle(chf, cycle):
+    """32x32 patches, b = 10, 3 levels, degree 2, BiCGStab to 1e-8."""
+    import torch
+    p = make_problem(32, 2, 10, 2, seed=0)
+    olv = oracle_levels(p, 3)
+    b_ = rhs(0, p.ndof)
+    ox, oit, ohist, _ = multilevel.bicgstab(olv[0].apply_a, lambda r: multilevel.vcycle(olv, 0, r, 2, cycle=cycle),
+                                            b_, 1e-8, 100)
+    A, L, _, _ = gpu_levels(p, 3, 2, 0)
+    chf.levels_set_cycle(L, chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_V2K0 if cycle == "v2k0" else chf.CYCLE_VKK)
+    x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    it, hist, true_res, rc = chf.bicgstab_solve(L, dev(b_), x, rtol=1e-8, maxit=100)
+    assert abs(it - oit) <= 1
+    assert hist[-1] <= 1e-8 and true_res < 1e-7
+    m = min(len(hist), len(ohist), 6)
+    assert np.allclose(hist[:m], ohist[:m], rtol=1e-6)
+    assert rel_err(host(x), ox) < 1e-6
+
+
+def test_bicgstab_zero_rhs_and_errors(chf):
+    import torch
+    p = make_problem(8, 2, 3, 2, seed=0)
+    A, L, _, _ = gpu_levels(p, 2, 2, 0)
+    z = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    x = torch.ones(p.ndof, dtype=torch.float64, device="cuda")
+    it, hist, tr, rc = chf.bicgstab_solve(L, z, x, rtol=1e-8, maxit=10)
+    assert it == 0 and rc == 0 and float(x.abs().max()) == 0.0
+    with pytest.raises(chf.ChfError) as ei:
+        chf.bicgstab_solve(L, z, x, rtol=-1.0, maxit=10)
+    assert ei.value.code == -1

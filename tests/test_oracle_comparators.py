@@ -7,7 +7,9 @@ cycle of Sec. 5:
   its degree-1 closed form; the minimax value 1 / cosh(k arccosh((b+a)/(b-a)));
 - Richardson smoothing against (I - omega M A)^k;
 - V(2k,0) against its two-level error operator built from dense matrices,
-  symmetry of V(k,k) for every smoother, and the lack of it for V(2k,0)."""
+  symmetry of V(k,k) for every smoother, and the lack of it for V(2k,0);
+- BiCGStab (the outer solver for V(2k,0)) against a dense solve, and its
+  one-step convergence with the exact preconditioner."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -153,3 +155,24 @@ def test_v2k0_not_symmetric():
     v1 = multilevel.vcycle(levels, 0, b1, 2, cycle="v2k0")
     v2 = multilevel.vcycle(levels, 0, b2, 2, cycle="v2k0")
     assert abs(v1 @ b2 - b1 @ v2) > 1e-6 * abs(v1 @ b2)
+
+
+def test_bicgstab_matches_dense_solve_with_nonsymmetric_preconditioner():
+    p, levels = _hier(n=16, levels=3)
+    a0 = levels[0]
+    b = np.random.default_rng(21).standard_normal(p.ndof)
+    x, it, hist, tr = multilevel.bicgstab(a0.apply_a, lambda r: multilevel.vcycle(levels, 0, r, 2, cycle="v2k0"),
+                                          b, 1e-10, 200)
+    xs = np.linalg.solve(a0.a.dense(), b)
+    assert tr < 1e-9 and hist[-1] <= 1e-10
+    assert np.abs(x - xs).max() < 1e-7 * np.abs(xs).max()
+    assert it < 60
+
+
+def test_bicgstab_exact_preconditioner_one_step():
+    # with K = A^{-1} the first half step already solves the system
+    p, levels = _hier(n=8, levels=2)
+    ad = levels[0].a.dense()
+    b = np.random.default_rng(22).standard_normal(p.ndof)
+    x, it, hist, tr = multilevel.bicgstab(lambda v: ad @ v, lambda r: np.linalg.solve(ad, r), b, 1e-12, 10)
+    assert it == 1 and len(hist) == 2 and tr < 1e-12
