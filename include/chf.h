@@ -103,9 +103,26 @@ int chf_fsai_setup(chf_bsr A, chf_pattern P, chf_dtype g_store, chf_fsai* out,
 int chf_fsai_destroy(chf_fsai G);
 /* G's FP64 blocks in pattern order (host double[nnz*b*b]). */
 int chf_fsai_export(chf_fsai G, double* vals);
-/* z = G^T G r (the preconditioner M r), device vectors of dtype. work: n. */
+/* z = G^T G r (the preconditioner M r), device vectors of dtype. work: n.
+ * For a nested factor (chf_fsai_nest) z = G0^T G1^T G1 G0 r. */
 int chf_fsai_apply(chf_fsai G, chf_dtype dtype, const void* r, void* z, void* work,
                    hipStream_t stream);
+
+/* ---------------------------------------------------- nested FSAI -------- */
+/* Sec. 2.2 with one nesting level. The inner factor is built for
+ * A1 = G0 A G0^T, where G0 is the outer (scaled) factor: block-FSAI and
+ * Algorithm 1 are invariant under that block-diagonal congruence, so
+ * M = G0^T G1^T G1 G0 equals the F^T S^{-1} F (F = F1 F0) of Sec. 2.2.
+ * chf_bsr_triple: *out = G A G^T (FP64, new handle owned by the caller),
+ * on the structural block pattern; G must be a plain factor (EINVAL for a
+ * nested one or mismatched sizes).
+ * chf_fsai_nest: *out = the nested factor of G0 (outer, built for A) and G1
+ * (inner, built for chf_bsr_triple(A, G0)); both are borrowed and must
+ * outlive *out; they must share nb, b and storage dtype. The nested handle
+ * is accepted wherever a factor is used (smoothers, Lanczos, apply, levels);
+ * chf_fsai_export refuses it (export its parts). */
+int chf_bsr_triple(chf_bsr A, chf_fsai G, chf_bsr* out);
+int chf_fsai_nest(chf_fsai G0, chf_fsai G1, chf_fsai* out);
 
 /* Largest eigenvalue of G A G^T (= of M A) by `iters` plain Lanczos steps
  * from the device start vector v0 (double[N], not modified); theta is the

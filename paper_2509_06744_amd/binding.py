@@ -12,7 +12,8 @@ __all__ = [
     "Bsr", "Pattern", "Fsai", "Levels", "Mlp", "LevelOpts",
     "bsr_create", "bsr_export", "bsr_spmv",
     "pattern_lower", "pattern_from_csr", "pattern_adaptive", "pattern_export",
-    "fsai_setup", "fsai_export", "fsai_apply", "lmax_lanczos", "cheb4_smooth", "cheb1_smooth", "richardson_smooth",
+    "fsai_setup", "fsai_export", "fsai_apply", "bsr_triple", "fsai_nest", "lmax_lanczos",
+    "cheb4_smooth", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
     "levels_set_beta", "levels_set_cycle", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
     "bicgstab_solve",
@@ -63,6 +64,8 @@ EXPORTED = {
     "chf_cheb1_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "chf_richardson_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "chf_levels_set_cycle": (C.c_int, [_vp, C.c_int, _dbl, C.c_int]),
+    "chf_bsr_triple": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
+    "chf_fsai_nest": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
     "chf_bicgstab_solve": (C.c_int, [_vp, _vp, _vp, _dbl, C.c_int, _pint, _vp, _pd, _vp]),
     "chf_levels_create": (C.c_int, [_vp, C.POINTER(_vp)]),
     "chf_levels_add_coarse": (C.c_int, [_vp, _i64, _vp, _vp, _vp, _vp]),
@@ -266,6 +269,22 @@ def fsai_setup(A: Bsr, P: Pattern, g_store=F64) -> Fsai:
         err.bad_row = bad.value
         raise err
     return Fsai(out)
+
+
+def bsr_triple(A: Bsr, G: Fsai) -> Bsr:
+    """G A G^T (the matrix the inner factor of nested FSAI is built for)."""
+    out = C.c_void_p()
+    _check(_fn("chf_bsr_triple")(A.h, G.h, C.byref(out)))
+    return Bsr(out)
+
+
+def fsai_nest(G0: Fsai, G1: Fsai) -> Fsai:
+    """Nested factor M = G0^T G1^T G1 G0; keeps G0 and G1 alive."""
+    out = C.c_void_p()
+    _check(_fn("chf_fsai_nest")(G0.h, G1.h, C.byref(out)))
+    n = Fsai(out)
+    n._parts = (G0, G1)
+    return n
 
 
 def fsai_export(G: Fsai, nnz: int, b: int):

@@ -659,11 +659,6 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
     return G.release();
 }
 
-void fsai_apply_impl(const chf_fsai_s& G, chf_dtype dt, const void* r, void* z, void* work, hipStream_t s) {
-    sell_spmv(G.g(dt), dt, r, work, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
-    sell_spmv(G.gt(dt), dt, work, z, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
-}
-
 // ---------------------------------------------------------------- Lanczos --
 // alpha_j = v . w, w <- w - alpha_j v - beta_{j-1} v_prev, beta_j = ||w||,
 // v_next = w / beta_j. Scalars stay on the device; the host reads them once.
@@ -698,8 +693,7 @@ void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const
     CHF_CHECK(iters >= 1, CHF_EINVAL, "iters must be >= 1");
     const int m = (int)std::min<int64_t>(iters, n);
     const Sell& sa = A->sell(dt == CHF_F64 ? CHF_F64 : CHF_F32, s);
-    const Sell& sg = G.g(dt);
-    const Sell& sgt = G.gt(dt);
+    const FactorOps fo = factor_ops(G, dt);
     DevBuf<double> vbuf(3 * n), w(n), t1(n), scal(2 * m + 4), part(RED_BLOCKS);
     double* va = vbuf.p;
     double* vb = vbuf.p + n;
@@ -716,10 +710,20 @@ void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const
     double* vprev = vb;
     double* spare = vc;
     for (int j = 0; j < m; ++j) {
-        // w = G A G^T v in FP64 arithmetic on the stored operators
-        sell_spmv(sgt, CHF_F64, v, w.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        // w = G A G^T v in FP64 arithmetic on the stored operators (nested:
+        // G = G1 G0, so w = G1 G0 A G0^T G1^T v)
+        if (fo.gi) {
+            sell_spmv(*fo.git, CHF_F64, v, t1.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+            sell_spmv(*fo.gt, CHF_F64, t1.p, w.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        } else {
+            sell_spmv(*fo.gt, CHF_F64, v, w.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        }
         sell_spmv(sa, CHF_F64, w.p, t1.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
-        sell_spmv(sg, CHF_F64, t1.p, w.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        sell_spmv(*fo.g, CHF_F64, t1.p, w.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        if (fo.gi) {
+            sell_spmv(*fo.gi, CHF_F64, w.p, t1.p, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+            CHF_HIP(hipMemcpyAsync(w.p, t1.p, n * 8, hipMemcpyDeviceToDevice, s));
+        }
         dot(CHF_F64, v, w.p, n, alphas + j, part.p, s);
         hipLaunchKernelGGL(k_lz_update, dim3(grid), dim3(256), 0, s, n, w.p, (const double*)v,
                            (const double*)vprev, (const double*)(alphas + j),
@@ -828,6 +832,7 @@ extern "C" int chf_fsai_destroy(chf_fsai G) {
 extern "C" int chf_fsai_export(chf_fsai G, double* vals) {
     return guarded([&] {
         CHF_CHECK(G && vals, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(!G->nest_outer, CHF_EINVAL, "nested factor: export its outer and inner factors");
         G->d_vals.download(vals, (size_t)G->nnz * G->b * G->b, 0);
         CHF_HIP(hipStreamSynchronize(0));
     });
@@ -841,8 +846,13 @@ extern "C" int chf_fsai_apply(chf_fsai G, chf_dtype dtype, const void* r, void* 
                   CHF_EINVAL, "dtype does not match the factor's storage");
         chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
         chf_dtype use = dtype == CHF_F64 ? CHF_F64 : G->store;
-        sell_spmv(G->g(use), vec, r, work, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
-        sell_spmv(G->gt(use), vec, work, z, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
+        const FactorOps fo = factor_ops(*G, use);
+        sell_spmv(*fo.g, vec, r, work, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
+        if (fo.gi) {   // z is the spare: work = G1^T G1 work
+            sell_spmv(*fo.gi, vec, work, z, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
+            sell_spmv(*fo.git, vec, z, work, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
+        }
+        sell_spmv(*fo.gt, vec, work, z, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
     });
 }
 

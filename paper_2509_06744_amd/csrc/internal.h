@@ -174,9 +174,31 @@ struct chf_fsai_s {
     chf::Sell g_lo, gt_lo;              // rounded copies (F32 / BF16) for mixed
     const chf::Sell& g(chf_dtype t) const { return t == CHF_F64 ? g64 : g_lo; }
     const chf::Sell& gt(chf_dtype t) const { return t == CHF_F64 ? gt64 : gt_lo; }
+    // nested factor (one level, Sec. 2.2): M = G0^T G1^T G1 G0 with G0 = outer,
+    // G1 = inner, both borrowed; a plain factor has neither
+    const chf_fsai_s* nest_outer = nullptr;
+    const chf_fsai_s* nest_inner = nullptr;
+    const chf_fsai_s& base() const { return nest_outer ? *nest_outer : *this; }
 };
 
 namespace chf {
+// The SpMV layouts of a factor in storage dtype t: g/gt the factor (the
+// outer one of a nested factor) and gi/git the inner one (null if plain).
+struct FactorOps {
+    const Sell* g;
+    const Sell* gt;
+    const Sell* gi;
+    const Sell* git;
+};
+inline FactorOps factor_ops(const chf_fsai_s& G, chf_dtype t) {
+    const chf_fsai_s& o = G.base();
+    FactorOps f{&o.g(t), &o.gt(t), nullptr, nullptr};
+    if (G.nest_inner) {
+        f.gi = &G.nest_inner->g(t);
+        f.git = &G.nest_inner->gt(t);
+    }
+    return f;
+}
 // Deterministic FP64 reductions (fixed grid, fixed tree).
 constexpr int RED_BLOCKS = 512;
 // out[0] = sum x_i y_i over n doubles/floats (vec dtype), accumulated in FP64.

@@ -10,12 +10,12 @@
 
 namespace chf {
 
-void cheb4_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double beta, int degree,
+void cheb4_impl(const Sell& A, const FactorOps& G, chf_dtype vec, double beta, int degree, const void* b, void* x,
+                bool x_is_zero, void* work, hipStream_t s);
+void cheb1_impl(const Sell& A, const FactorOps& G, chf_dtype vec, double alpha, double beta, int degree,
                 const void* b, void* x, bool x_is_zero, void* work, hipStream_t s);
-void cheb1_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double alpha, double beta, int degree,
-                const void* b, void* x, bool x_is_zero, void* work, hipStream_t s);
-void richardson_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double omega, int degree,
-                     const void* b, void* x, bool x_is_zero, void* work, hipStream_t s);
+void richardson_impl(const Sell& A, const FactorOps& G, chf_dtype vec, double omega, int degree, const void* b,
+                     void* x, bool x_is_zero, void* work, hipStream_t s);
 chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store, int64_t* bad_row,
                             hipStream_t s);
 void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const double* v0, double safety,
@@ -501,17 +501,16 @@ static void smooth_level(chf_levels_s& H, int l, int degree, const void* b, void
     chf_level_s& L = H.lev[l];
     const Sell& A = level_A(H, l, s);
     const chf_dtype gdt = H.vec == CHF_F64 ? CHF_F64 : L.G->store;
-    const Sell& G = L.G->g(gdt);
-    const Sell& Gt = L.G->gt(gdt);
+    const FactorOps G = factor_ops(*L.G, gdt);
     switch (H.smoother) {
         case CHF_SMOOTH_CHEB1:
-            cheb1_impl(A, G, Gt, H.vec, H.sm_param * L.beta, L.beta, degree, b, x, x_is_zero, L.work.p, s);
+            cheb1_impl(A, G, H.vec, H.sm_param * L.beta, L.beta, degree, b, x, x_is_zero, L.work.p, s);
             break;
         case CHF_SMOOTH_RICHARDSON:
-            richardson_impl(A, G, Gt, H.vec, H.sm_param, degree, b, x, x_is_zero, L.work.p, s);
+            richardson_impl(A, G, H.vec, H.sm_param, degree, b, x, x_is_zero, L.work.p, s);
             break;
         default:
-            cheb4_impl(A, G, Gt, H.vec, L.beta, degree, b, x, x_is_zero, L.work.p, s);
+            cheb4_impl(A, G, H.vec, L.beta, degree, b, x, x_is_zero, L.work.p, s);
     }
 }
 

@@ -8,6 +8,8 @@
 //
 // Each step is three kernels: r = b - A x (skipped in the first step when x
 // starts at zero), t = G r, and z = G^T t fused with the update of p and x.
+// With a nested factor (Sec. 2.2), M = G0^T G1^T G1 G0 and the middle of the
+// step becomes t = G0 r, t' = G1 t, t = G1^T t' (five kernels).
 #include <cmath>
 #include <vector>
 
@@ -66,8 +68,9 @@ static StepCoef richardson_coef(double omega, int k) {
     return s;
 }
 
-static void poly_smooth_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, const StepCoef& cf,
-                             const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
+static void poly_smooth_impl(const Sell& A, const Sell& G, const Sell& Gt, const Sell* Gi, const Sell* Git,
+                             chf_dtype vec, const StepCoef& cf, const void* b, void* x, bool x_is_zero, void* work,
+                             hipStream_t s) {
     const int k = (int)cf.c.size();
     const int64_t n = A.nb * (int64_t)A.b;
     const size_t es = vec_size(vec);
@@ -81,36 +84,44 @@ static void poly_smooth_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_d
         sell_spmv(A, vec, x, r, b, EPI_RES, nullptr, nullptr, 0, 0, s);
         r0 = r;
     }
-    sell_spmv(G, vec, r0, t, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+    // t = G r (nested: t = G1^T G1 G0 r, with r's buffer as the spare)
+    auto gmid = [&](const void* rin) {
+        sell_spmv(G, vec, rin, t, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        if (Gi) {
+            sell_spmv(*Gi, vec, t, r, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+            sell_spmv(*Git, vec, r, t, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        }
+    };
+    gmid(r0);
     sell_spmv(Gt, vec, t, nullptr, nullptr, x_is_zero ? EPI_CHEB_FIRST0 : EPI_CHEB_FIRST, p, x, 0.0, cf.c[0], s);
     for (int i = 1; i < k; ++i) {
         sell_spmv(A, vec, x, r, b, EPI_RES, nullptr, nullptr, 0, 0, s);
-        sell_spmv(G, vec, r, t, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+        gmid(r);
         sell_spmv(Gt, vec, t, nullptr, nullptr, EPI_CHEB, p, x, cf.a[i], cf.c[i], s);
     }
 }
 
 static void check_degree(int degree) { CHF_CHECK(degree >= 1, CHF_EINVAL, "degree must be >= 1"); }
 
-void cheb4_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double beta, int degree,
-                const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
+void cheb4_impl(const Sell& A, const FactorOps& G, chf_dtype vec, double beta, int degree, const void* b, void* x,
+                bool x_is_zero, void* work, hipStream_t s) {
     check_degree(degree);
     CHF_CHECK(beta > 0 && std::isfinite(beta), CHF_EINVAL, "beta must be positive and finite");
-    poly_smooth_impl(A, G, Gt, vec, cheb4_coef(beta, degree), b, x, x_is_zero, work, s);
+    poly_smooth_impl(A, *G.g, *G.gt, G.gi, G.git, vec, cheb4_coef(beta, degree), b, x, x_is_zero, work, s);
 }
 
-void cheb1_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double alpha, double beta, int degree,
+void cheb1_impl(const Sell& A, const FactorOps& G, chf_dtype vec, double alpha, double beta, int degree,
                 const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
     check_degree(degree);
     CHF_CHECK(alpha > 0 && beta > alpha && std::isfinite(beta), CHF_EINVAL, "need 0 < alpha < beta < inf");
-    poly_smooth_impl(A, G, Gt, vec, cheb1_coef(alpha, beta, degree), b, x, x_is_zero, work, s);
+    poly_smooth_impl(A, *G.g, *G.gt, G.gi, G.git, vec, cheb1_coef(alpha, beta, degree), b, x, x_is_zero, work, s);
 }
 
-void richardson_impl(const Sell& A, const Sell& G, const Sell& Gt, chf_dtype vec, double omega, int degree,
-                     const void* b, void* x, bool x_is_zero, void* work, hipStream_t s) {
+void richardson_impl(const Sell& A, const FactorOps& G, chf_dtype vec, double omega, int degree, const void* b,
+                     void* x, bool x_is_zero, void* work, hipStream_t s) {
     check_degree(degree);
     CHF_CHECK(omega > 0 && std::isfinite(omega), CHF_EINVAL, "omega must be positive and finite");
-    poly_smooth_impl(A, G, Gt, vec, richardson_coef(omega, degree), b, x, x_is_zero, work, s);
+    poly_smooth_impl(A, *G.g, *G.gt, G.gi, G.git, vec, richardson_coef(omega, degree), b, x, x_is_zero, work, s);
 }
 
 }  // namespace chf
@@ -129,28 +140,28 @@ int with_operands(chf_bsr A, chf_fsai G, chf_dtype dtype, const void* b, void* x
                   "dtype must be F64 or the factor's storage dtype");
         chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
         const Sell& sa = A->sell(vec, stream);
-        f(sa, G->g(dtype), G->gt(dtype), vec);
+        f(sa, factor_ops(*G, dtype), vec);
     });
 }
 }  // namespace
 
 extern "C" int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree, const void* b,
                                 void* x, int x_is_zero, void* work, hipStream_t stream) {
-    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const Sell& g, const Sell& gt, chf_dtype vec) {
-        cheb4_impl(sa, g, gt, vec, beta, degree, b, x, x_is_zero != 0, work, stream);
+    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const FactorOps& g, chf_dtype vec) {
+        cheb4_impl(sa, g, vec, beta, degree, b, x, x_is_zero != 0, work, stream);
     });
 }
 
 extern "C" int chf_cheb1_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double alpha, double beta, int degree,
                                 const void* b, void* x, int x_is_zero, void* work, hipStream_t stream) {
-    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const Sell& g, const Sell& gt, chf_dtype vec) {
-        cheb1_impl(sa, g, gt, vec, alpha, beta, degree, b, x, x_is_zero != 0, work, stream);
+    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const FactorOps& g, chf_dtype vec) {
+        cheb1_impl(sa, g, vec, alpha, beta, degree, b, x, x_is_zero != 0, work, stream);
     });
 }
 
 extern "C" int chf_richardson_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double omega, int degree,
                                      const void* b, void* x, int x_is_zero, void* work, hipStream_t stream) {
-    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const Sell& g, const Sell& gt, chf_dtype vec) {
-        richardson_impl(sa, g, gt, vec, omega, degree, b, x, x_is_zero != 0, work, stream);
+    return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const FactorOps& g, chf_dtype vec) {
+        richardson_impl(sa, g, vec, omega, degree, b, x, x_is_zero != 0, work, stream);
     });
 }
