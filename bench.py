@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--no-nested", action="store_true")
     ap.add_argument("--no-setup3d", action="store_true")
     ap.add_argument("--setup3d-grid", type=int, default=64, help="3D patch grid of the batched set-up leg")
     ap.add_argument("--setup3d-tmax", type=int, default=23)
@@ -205,6 +206,61 @@ def comparators_leg(args, chf, torch, dev, H, A, bd, N, k):
         out[name] = rec
         log(f"comparator {name}: {rec}")
     chf.levels_set_cycle(H, chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_VKK)
+    return out
+
+
+def nested_leg(args, chf, torch, dev, A, bd, N, k, pro, bases, v0, H_plain, plain_setup_ms):
+    """Nested block-FSAI (Sec. 2.2, one nesting level, Algorithm 1 with the same
+    t_max on both levels) against plain FSAI with t_max = 8 on the same 512^2
+    hierarchy: set-up time, energy-norm cycle factor, PCG to 1e-8 and the time
+    of one level-0 smoother application (five kernels per step instead of
+    three). Sec. 5 observes that nested t_max = c behaves like plain 2c."""
+    from paper_2509_06744_amd import learned
+    from problems import uniform_start
+    e0 = torch.from_numpy(uniform_start(0, N)).to(dev)
+    out = {}
+
+    def measure(H, name, setup_ms):
+        rec = {"levels_setup_ms": round(setup_ms, 1)}
+        rho, ncyc = learned.energy_factor(H, A, e0, maxit=30)
+        rec["rho_A"], rec["cycles"] = round(rho, 5), ncyc
+        xs = torch.zeros(N, dtype=torch.float64, device=dev)
+        chf.pcg_solve(H, bd, xs, rtol=1e-8, maxit=200, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it, hist, tr, rc = chf.pcg_solve(H, bd, xs, rtol=1e-8, maxit=200, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        rec.update({"pcg_iterations": it, "pcg_time_ms": round(1e3 * el, 2), "converged": rc == 0,
+                    "true_relres": tr})
+        _, G0, _ = chf.levels_get(H, 0)
+        beta0 = chf.levels_get_beta(H, 0)
+        x = torch.zeros(N, dtype=torch.float64, device=dev)
+        work = torch.zeros(3 * N, dtype=torch.float64, device=dev)
+        for _ in range(2):
+            chf.cheb4_smooth(A, G0, beta0, k, bd, x, x_is_zero=False, work=work)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(10):
+            chf.cheb4_smooth(A, G0, beta0, k, bd, x, x_is_zero=False, work=work)
+        ev1.record()
+        torch.cuda.synchronize()
+        rec["smoother_ms_per_application"] = round(ev0.elapsed_time(ev1) / 10, 4)
+        out[name] = rec
+        log(f"nested leg {name}: {rec}")
+
+    measure(H_plain, f"plain_tmax{args.tmax}", plain_setup_ms)
+    for tm in (4, 8):
+        H = chf.levels_create(A)
+        for ps, basis in zip(pro, bases):
+            chf.levels_add_coarse(H, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
+        chf.levels_set_nesting(H, 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        chf.levels_setup(H, degree=k, pattern=1, tmax=tm, v0=v0)
+        torch.cuda.synchronize()
+        measure(H, f"nested_tmax{tm}", 1e3 * (time.perf_counter() - t))
+        H.destroy()
     return out
 
 
@@ -463,6 +519,9 @@ def main():
 
     if not args.no_comparators:
         out["comparators"] = comparators_leg(args, chf, torch, dev, H, A, bd, N, k)
+    if not args.no_nested:
+        out["nested"] = nested_leg(args, chf, torch, dev, A, bd, N, k, pro, bases, v0, H,
+                                   setup64["levels_setup_ms"])
     if not args.no_learned:
         out["learned"] = learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases)
     if not args.no_setup3d:

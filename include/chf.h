@@ -190,6 +190,12 @@ int chf_levels_info(chf_levels L, int* nlevels, int64_t* nb_per_level /* [nlevel
 int chf_levels_get(chf_levels L, int level, chf_bsr* A, chf_fsai* G, chf_pattern* P);
 int chf_levels_get_beta(chf_levels L, int level, double* beta);
 int chf_levels_set_beta(chf_levels L, int level, double beta);
+/* Nested block-FSAI on every smoothed level (Sec. 2.2, one nesting level,
+ * the same t_max and tau on both levels as in Sec. 5): nest = 1 builds the
+ * outer factor G0 for A_l, the inner factor for G0 A_l G0^T from Algorithm 1,
+ * and smooths with M = G0^T G1^T G1 G0; nest = 0 (default) is plain FSAI.
+ * Before chf_levels_setup; with nest = 1 opts->pattern must be 1 (EINVAL). */
+int chf_levels_set_nesting(chf_levels L, int nest);
 /* Smoother and cycle shape of the hierarchy (default: fourth kind, V(k,k)).
  * smoother: CHF_SMOOTH_CHEB4 (Algorithm 3 on [0, beta_l]; param ignored),
  * CHF_SMOOTH_CHEB1 (Algorithm 2 on [param * beta_l, beta_l], 0 < param < 1),

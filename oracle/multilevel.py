@@ -46,8 +46,11 @@ class Level:
     basis: np.ndarray | None = None    # block-diagonal T of P = T (P_s (x) I_b)
     chol: tuple | None = None
     a_sp: sp.bsr_matrix = field(default=None, repr=False)
+    g1: Bsr | None = None         # inner factor of nested FSAI (Sec. 2.2), or None
     g_sp: sp.bsr_matrix = field(default=None, repr=False)
     gt_sp: sp.bsr_matrix = field(default=None, repr=False)
+    g1_sp: sp.bsr_matrix = field(default=None, repr=False)
+    g1t_sp: sp.bsr_matrix = field(default=None, repr=False)
     pb: sp.csr_matrix = field(default=None, repr=False)
 
     def finish(self):
@@ -55,6 +58,9 @@ class Level:
         if self.g is not None:
             self.g_sp = self.g.scipy()
             self.gt_sp = self.g_sp.T.tobsr(blocksize=(self.a.b, self.a.b))
+        if self.g1 is not None:
+            self.g1_sp = self.g1.scipy()
+            self.g1t_sp = self.g1_sp.T.tobsr(blocksize=(self.a.b, self.a.b))
         if self.p_s is not None:
             self.pb = block_prolongator(self.p_s, self.a.b, self.basis)
         return self
@@ -63,7 +69,16 @@ class Level:
         return self.a_sp @ v
 
     def apply_m(self, v):
+        if self.g1 is not None:
+            return self.gt_sp @ (self.g1t_sp @ (self.g1_sp @ (self.g_sp @ v)))
         return self.gt_sp @ (self.g_sp @ v)
+
+    def apply_b(self, v):
+        """v -> G^ A G^T v with G^ = G (or G1 G0 when nested): the operator
+        whose largest eigenvalue bounds the spectrum of M A."""
+        if self.g1 is not None:
+            return self.g1_sp @ (self.g_sp @ (self.a_sp @ (self.gt_sp @ (self.g1t_sp @ v))))
+        return self.g_sp @ (self.a_sp @ (self.gt_sp @ v))
 
 
 def coarse_factor(a: Bsr):

@@ -15,7 +15,7 @@ __all__ = [
     "fsai_setup", "fsai_export", "fsai_apply", "bsr_triple", "fsai_nest", "lmax_lanczos",
     "cheb4_smooth", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
-    "levels_set_beta", "levels_set_cycle", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
+    "levels_set_beta", "levels_set_cycle", "levels_set_nesting", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
     "bicgstab_solve",
     "mlp_candidates", "mlp_features", "mlp_create", "mlp_get_params", "mlp_forward",
     "mlp_loss_grad", "mlp_train_step", "mlp_propose", "mlp_labels", "mlp_train",
@@ -65,6 +65,7 @@ EXPORTED = {
     "chf_richardson_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "chf_levels_set_cycle": (C.c_int, [_vp, C.c_int, _dbl, C.c_int]),
     "chf_bsr_triple": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
+    "chf_levels_set_nesting": (C.c_int, [_vp, C.c_int]),
     "chf_fsai_nest": (C.c_int, [_vp, _vp, C.POINTER(_vp)]),
     "chf_bicgstab_solve": (C.c_int, [_vp, _vp, _vp, _dbl, C.c_int, _pint, _vp, _pd, _vp]),
     "chf_levels_create": (C.c_int, [_vp, C.POINTER(_vp)]),
@@ -381,6 +382,10 @@ def levels_get_beta(L: Levels, level: int) -> float:
 
 def levels_set_beta(L: Levels, level: int, beta: float):
     _check(_fn("chf_levels_set_beta")(L.h, int(level), float(beta)))
+
+
+def levels_set_nesting(L: Levels, nest=1):
+    _check(_fn("chf_levels_set_nesting")(L.h, int(nest)))
 
 
 def levels_set_cycle(L: Levels, smoother=SMOOTH_CHEB4, param=0.0, cycle=CYCLE_VKK):

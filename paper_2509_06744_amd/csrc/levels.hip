@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstring>
 
+#include <memory>
+
 #include "internal.h"
 #include "kernels_common.h"
 
@@ -18,6 +20,7 @@ void richardson_impl(const Sell& A, const FactorOps& G, chf_dtype vec, double om
                      void* x, bool x_is_zero, void* work, hipStream_t s);
 chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store, int64_t* bad_row,
                             hipStream_t s);
+chf_bsr_s* bsr_triple_impl(chf_bsr A, const chf_fsai_s& G, hipStream_t s);
 void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const double* v0, double safety,
                   double* beta_out, double* theta_out, hipStream_t s);
 chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_t s);
@@ -385,7 +388,9 @@ struct chf_level_s {
     chf_pattern P = nullptr;
     bool preset = false;                // P given by the caller
 
-    chf_fsai G = nullptr;
+    chf_fsai G = nullptr;               // the smoother's factor (nested handle when nesting)
+    chf_fsai G0 = nullptr, G1 = nullptr; // outer and inner factors of a nested G
+    chf_pattern P1 = nullptr;           // inner pattern
     double beta = 0.0;
     // prolongation from the next coarser level (host + device CSR)
     int64_t nc = 0;
@@ -415,11 +420,15 @@ struct chf_levels_s {
     int smoother = CHF_SMOOTH_CHEB4;   // smoother of every level but the coarsest
     double sm_param = 0.0;             // rho (first kind: alpha_l = rho beta_l) or omega (Richardson)
     int cycle = CHF_CYCLE_VKK;
+    int nest = 0;                      // 1: nested block-FSAI with one level (Sec. 2.2)
     DevBuf<double> pcg_buf, scal, part;
     int64_t pcg_n = 0;
     ~chf_levels_s() {
         for (auto& l : lev) {
             if (l.G) delete l.G;
+            if (l.G0) delete l.G0;
+            if (l.G1) delete l.G1;
+            if (l.P1) delete l.P1;
             if (l.P) delete l.P;
             if (l.own_A && l.A) delete l.A;
         }
@@ -714,6 +723,7 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
         CHF_CHECK(!H->ready, CHF_EINVAL, "hierarchy already set up");
         CHF_CHECK(opts->degree >= 1, CHF_EINVAL, "degree must be >= 1");
         CHF_CHECK(opts->pattern >= 0 && opts->pattern <= 2, CHF_EINVAL, "bad pattern mode");
+        CHF_CHECK(!H->nest || opts->pattern == 1, CHF_EINVAL, "nesting needs the adaptive pattern (pattern = 1)");
         CHF_CHECK(opts->dtype == CHF_F64 || opts->dtype == CHF_F32 || opts->dtype == CHF_BF16, CHF_EINVAL,
                   "bad dtype");
         if (bad_row) *bad_row = -1;
@@ -741,7 +751,22 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
                 if (st != CHF_OK) fail(st, chf_last_error());
                 L.P = P;
             }
-            L.G = fsai_setup_impl(L.A, *L.P, opts->dtype, bad_row, s);
+            if (H->nest) {
+                // outer factor for A_l, inner factor for G0 A_l G0^T with
+                // Algorithm 1's pattern (same t_max and tau)
+                L.G0 = fsai_setup_impl(L.A, *L.P, opts->dtype, bad_row, s);
+                std::unique_ptr<chf_bsr_s> A1(bsr_triple_impl(L.A, *L.G0, s));
+                L.P1 = adaptive_pattern_impl(A1.get(), opts->tmax, opts->tau, s);
+                L.G1 = fsai_setup_impl(A1.get(), *L.P1, opts->dtype, bad_row, s);
+                L.G = new chf_fsai_s;
+                L.G->nb = L.G0->nb;
+                L.G->b = L.G0->b;
+                L.G->store = L.G0->store;
+                L.G->nest_outer = L.G0;
+                L.G->nest_inner = L.G1;
+            } else {
+                L.G = fsai_setup_impl(L.A, *L.P, opts->dtype, bad_row, s);
+            }
             if (v0 && v0[l]) {
                 lanczos_impl(L.A, *L.G, opts->dtype, opts->lanczos_iters, v0[l], opts->safety, &L.beta, nullptr, s);
             }
@@ -816,6 +841,15 @@ extern "C" int chf_vcycle(chf_levels H, const void* b, void* x, int x_is_zero, h
         check_ready(H);
         CHF_CHECK(b && x, CHF_EINVAL, "NULL vector");
         vcycle_rec(*H, 0, b, x, x_is_zero != 0, stream);
+    });
+}
+
+extern "C" int chf_levels_set_nesting(chf_levels H, int nest) {
+    return guarded([&] {
+        CHF_CHECK(H, CHF_EINVAL, "NULL hierarchy");
+        CHF_CHECK(!H->ready, CHF_EINVAL, "hierarchy already set up");
+        CHF_CHECK(nest == 0 || nest == 1, CHF_EINVAL, "nesting depth must be 0 or 1");
+        H->nest = nest;
     });
 }
 

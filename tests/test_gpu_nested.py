@@ -99,3 +99,38 @@ def test_nested_errors(chf):
     with pytest.raises(chf.ChfError) as ei:
         chf.fsai_nest(G0, Gq)
     assert ei.value.code == -1
+
+
+def test_nested_hierarchy_vcycle_and_pcg(chf):
+    """16x16 patches, b = 10, 3 levels, adaptive t_max 3 with one nesting
+    level: Lanczos bounds, one V(2,2) cycle and PCG against the oracle."""
+    import torch
+    import paper_2509_06744_amd as m
+    from oracle import multilevel
+    from problems import level_basis
+    from tests.helpers import hierarchy_inputs, oracle_levels
+    p = make_problem(16, 2, 10, 2, seed=0)
+    olv = oracle_levels(p, 3, "adaptive", 3, nest=True)
+    A = upload(p)
+    pro, starts = hierarchy_inputs(p.n, p.dim, p.b, 3, 0)
+    L = m.levels_create(A)
+    for ps, basis in zip(pro, level_basis(p, 3)):
+        ps = ps.tocsr()
+        m.levels_add_coarse(L, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
+    m.levels_set_nesting(L, 1)
+    m.levels_setup(L, degree=2, pattern=1, tmax=3, v0=[dev(s) for s in starts[:-1]])
+    for l in range(2):
+        assert abs(m.levels_get_beta(L, l) - olv[l].beta) < 1e-9 * olv[l].beta
+        m.levels_set_beta(L, l, olv[l].beta)
+    b_ = rhs(0, p.ndof)
+    want = multilevel.vcycle(olv, 0, b_, 2)
+    x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    m.vcycle(L, dev(b_), x, x_is_zero=True)
+    assert rel_err(host(x), want) < 1e-11
+    _, oit, _, _ = multilevel.pcg(olv[0].apply_a, lambda r: multilevel.vcycle(olv, 0, r, 2), b_, 1e-8, 100)
+    x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    it, hist, tr, rc = m.pcg_solve(L, dev(b_), x, rtol=1e-8, maxit=100)
+    assert abs(it - oit) <= 1 and tr < 1e-7
+    L2 = m.levels_create(A)
+    with pytest.raises(m.ChfError):
+        m.levels_set_nesting(L2, 2)
