@@ -61,10 +61,24 @@ __global__ void k_sell_pack(int64_t total, int b, int S, int L, int V, const int
          e += (int64_t)gridDim.x * blockDim.x) {
         int64_t slot = e / bl;
         int rem = (int)(e - slot * bl);
-        int q = rem / LV;
-        int rem2 = rem - q * LV;
-        int lane = rem2 / V;
-        int c = q * V + (rem2 - lane * V);
+        int lane, c;
+        if (V == 4) {
+            // b = 10: runs of 4, 4 and 2 columns (L * 4, L * 4, L * 2 values)
+            if (rem < 8 * L) {
+                const int q = rem / (4 * L), rem2 = rem - q * 4 * L;
+                lane = rem2 / 4;
+                c = q * 4 + (rem2 - lane * 4);
+            } else {
+                const int rem2 = rem - 8 * L;
+                lane = rem2 / 2;
+                c = 8 + (rem2 - lane * 2);
+            }
+        } else {
+            const int q = rem / LV;
+            const int rem2 = rem - q * LV;
+            lane = rem2 / V;
+            c = q * V + (rem2 - lane * V);
+        }
         int lr = lane / b, r = lane - lr * b;
         int64_t sb = src[slot * S + lr];
         double v = 0.0;
@@ -76,9 +90,11 @@ __global__ void k_sell_pack(int64_t total, int b, int S, int L, int V, const int
     }
 }
 
-// Lane vector width of the layout: pairs of columns for the block sizes with
-// a specialised SpMV (16-byte FP64 loads for b = 10).
-static int sell_vec_width(int b) { return b == 10 ? 2 : 1; }
+// Lane vector width of the layout for the block sizes with a specialised
+// SpMV: b = 10 stores pairs of columns for FP64 (16-byte loads) and runs of
+// 4, 4 and 2 columns for 4- and 2-byte storage (16- and 8-byte loads for
+// FP32), marked V = 4.
+static int sell_vec_width(int b, chf_dtype t) { return b == 10 ? (t == CHF_F64 ? 2 : 4) : 1; }
 
 void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, bool transpose,
                 chf_dtype dtype, hipStream_t s) {
@@ -86,7 +102,7 @@ void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, boo
     out.b = plan.b;
     out.S = plan.S;
     out.L = plan.L;
-    out.V = sell_vec_width(plan.b);
+    out.V = sell_vec_width(plan.b, dtype);
     out.nslices = plan.nslices;
     out.nslots = plan.nslots;
     out.dtype = dtype;
@@ -182,6 +198,40 @@ struct Pair<2, bf16_t, TV, NTL> {
     }
 };
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <typename TV, bool NTL>
+struct Pair<4, float, TV, NTL> {
+    __device__ static inline TV dot(const float* v, const TV* x) {
+        f4v a;
+        if constexpr (NTL)
+            a = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(v));
+        else
+            a = *reinterpret_cast<const f4v*>(v);
+        if constexpr (sizeof(TV) == 4) {
+            const float2 y0 = *reinterpret_cast<const float2*>(x);
+            const float2 y1 = *reinterpret_cast<const float2*>(x + 2);
+            return (a.x * y0.x + a.y * y0.y) + (a.z * y1.x + a.w * y1.y);
+        } else {
+            return ((TV)a.x * x[0] + (TV)a.y * x[1]) + ((TV)a.z * x[2] + (TV)a.w * x[3]);
+        }
+    }
+};
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+template <typename TV, bool NTL>
+struct Pair<4, bf16_t, TV, NTL> {
+    __device__ static inline TV dot(const bf16_t* v, const TV* x) {
+        u2v u;
+        if constexpr (NTL)
+            u = __builtin_nontemporal_load(reinterpret_cast<const u2v*>(v));
+        else
+            u = *reinterpret_cast<const u2v*>(v);
+        return ((TV)bf16_bits_to_f32((uint16_t)(u.x & 0xffffu)) * x[0] +
+                (TV)bf16_bits_to_f32((uint16_t)(u.x >> 16)) * x[1]) +
+               ((TV)bf16_bits_to_f32((uint16_t)(u.y & 0xffffu)) * x[2] +
+                (TV)bf16_bits_to_f32((uint16_t)(u.y >> 16)) * x[3]);
+    }
+};
+
 __device__ inline int64_t xcd_slice_block(int64_t nwork_blocks) {
     // gridDim.x is a multiple of 8; block id b runs on XCD b % 8
     const int64_t per = gridDim.x / 8;
@@ -206,7 +256,21 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, 
     if (row >= nb) return;
     const int j0 = soff[slice], j1 = soff[slice + 1];
     TV acc = 0;
-    if constexpr (BT > 0) {
+    if constexpr (BT == 10 && V == 4) {
+        // runs of 4, 4 and 2 columns per slot (16-, 16- and 8-byte loads)
+        const int64_t stride = (int64_t)10 * L;
+        const TA* v = vals + (int64_t)j0 * stride;
+        const int* cp = cols + (int64_t)j0 * S + lr;
+#pragma unroll 2
+        for (int j = j0; j < j1; ++j) {
+            const TV* xc = x + (int64_t)(*cp) * 10;
+            acc += Pair<4, TA, TV, NTL>::dot(v + lane * 4, xc);
+            acc += Pair<4, TA, TV, NTL>::dot(v + 4 * L + lane * 4, xc + 4);
+            acc += Pair<2, TA, TV, NTL>::dot(v + 8 * L + lane * 2, xc + 8);
+            v += stride;
+            cp += S;
+        }
+    } else if constexpr (BT > 0) {
         constexpr int NQ = BT / V;
         const int64_t stride = (int64_t)NQ * L * V;
         const TA* v = vals + (int64_t)j0 * stride + lane * V;
@@ -286,9 +350,14 @@ static void launch_spmv_t(const Sell& A, const void* x, void* y, const void* bv,
 template <typename TA, typename TV>
 static void launch_spmv_b(const Sell& A, const void* x, void* y, const void* bv, int epi, void* p, void* xo,
                           double alpha, double beta, hipStream_t s) {
-    CHF_CHECK(A.V == sell_vec_width(A.b), CHF_EDEVICE, "SpMV layout width mismatch");
+    CHF_CHECK(A.V == sell_vec_width(A.b, A.dtype), CHF_EDEVICE, "SpMV layout width mismatch");
     switch (A.b) {
-        case 10: launch_spmv_t<10, 2, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+        case 10:
+            if constexpr (sizeof(TA) == 8)
+                launch_spmv_t<10, 2, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
+            else
+                launch_spmv_t<10, 4, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
+            break;
         case 21: launch_spmv_t<21, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
         default: launch_spmv_t<0, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
     }
