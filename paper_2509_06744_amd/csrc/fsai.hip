@@ -163,7 +163,7 @@ __device__ inline void tri_decode(int t, int& I, int& J) {
 __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                const double* __restrict__ a_vals, const int64_t* __restrict__ p_rowptr,
                                const int* __restrict__ p_col, double* __restrict__ g_vals, double* tiles,
-                               double* panel, double* Zl, double* invs, double* part, int* idx, int* sh_flag,
+                               double* panel, double* invs, double* part, int* idx, int* sh_flag,
                                int* bad_row) {
     constexpr int NT = 256;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -172,60 +172,96 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
     const int n = m * b;
     const int T = (n + 15) / 16;
     const int* cols = p_col + p0;
-    for (int t = tid; t < m * m; t += NT) {
-        int a = t / m, c = t - a * m;
-        int e = -1;
-        if (c <= a) {
-            int row = cols[a], want = cols[c];
-            int lo = a_rowptr[row], hi = a_rowptr[row + 1];
-            while (lo < hi) {
-                int mid = (lo + hi) >> 1;
-                if (a_col[mid] < want) lo = mid + 1; else hi = mid;
+    // block map idx[a m + c] = position of A[P_k[a], P_k[c]] in A (or -1), c <= a;
+    // each thread runs IS binary searches side by side so their loads overlap
+    constexpr int IS = 4;
+    for (int t0 = tid; t0 < m * m; t0 += IS * NT) {
+        int lo[IS], hi[IS], end[IS], want[IS];
+#pragma unroll
+        for (int s = 0; s < IS; ++s) {
+            const int t = t0 + s * NT;
+            const int a = t / m, c = t - a * m;
+            lo[s] = hi[s] = end[s] = 0;
+            want[s] = -1;
+            if (t < m * m && c <= a) {
+                const int row = cols[a];
+                lo[s] = a_rowptr[row];
+                hi[s] = end[s] = a_rowptr[row + 1];
+                want[s] = cols[c];
             }
-            if (lo < a_rowptr[row + 1] && a_col[lo] == want) e = lo;
         }
-        idx[t] = e;
+        for (;;) {
+            bool any = false;
+#pragma unroll
+            for (int s = 0; s < IS; ++s) {
+                if (lo[s] < hi[s]) {
+                    any = true;
+                    const int mid = (lo[s] + hi[s]) >> 1;
+                    if (a_col[mid] < want[s]) lo[s] = mid + 1; else hi[s] = mid;
+                }
+            }
+            if (!any) break;
+        }
+#pragma unroll
+        for (int s = 0; s < IS; ++s) {
+            const int t = t0 + s * NT;
+            if (t < m * m) idx[t] = (want[s] >= 0 && lo[s] < end[s] && a_col[lo[s]] == want[s]) ? lo[s] : -1;
+        }
     }
     __syncthreads();
     const int ntiles = T * (T + 1) / 2;
-    for (int64_t e = tid; e < (int64_t)ntiles * 256; e += NT) {
+    // tiles of the lower triangle: one lane fills 8 entries of a tile row, with
+    // its 8 gathers from A issued before any is used (unused lanes read entry 0);
+    // entries above the diagonal are 0, padding rows and columns are identity
+    for (int u = tid; u < ntiles * 32; u += NT) {
         int I, J;
-        tri_decode((int)(e >> 8), I, J);
-        const int rc = (int)(e & 255), r = rc >> 4, c = rc & 15;
-        const int i = 16 * I + r, j = 16 * J + c;
-        double v;
-        if (i < n && j < n) {
-            if (j > i) {
-                v = 0.0;
-            } else {
-                const int a = i / b, ra = i - a * b, cb = j / b, rcc = j - cb * b;
-                const int ee = idx[a * m + cb];
-                v = ee >= 0 ? a_vals[(int64_t)ee * b * b + ra * b + rcc] : 0.0;
-            }
-        } else {
-            v = (i == j) ? 1.0 : 0.0;
+        tri_decode(u >> 5, I, J);
+        const int r = (u >> 1) & 15, c0 = (u & 1) << 3;
+        const int i = 16 * I + r, j0 = 16 * J + c0;
+        const bool row_in = i < n;
+        const int a = row_in ? i / b : 0, ra = row_in ? i - a * b : 0;
+        int cb = j0 / b, rc = j0 - cb * b;
+        double v[8];
+        bool take[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = j0 + q;
+            const int ee = (row_in && j < n && j <= i) ? idx[a * m + cb] : -1;
+            take[q] = ee >= 0;
+            v[q] = a_vals[take[q] ? (int64_t)ee * b * b + ra * b + rc : 0];
+            if (++rc == b) { rc = 0; ++cb; }
         }
-        tiles[e] = v;
+        double2* dst = reinterpret_cast<double2*>(tile_at(tiles, I, J) + r * 16 + c0);
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+            const double d0 = (i == j0 + q) ? 1.0 : 0.0, d1 = (i == j0 + q + 1) ? 1.0 : 0.0;
+            dst[q >> 1] = make_double2(take[q] ? v[q] : d0, take[q + 1] ? v[q + 1] : d1);
+        }
     }
     if (tid == 0) sh_flag[0] = 1;
     __syncthreads();
     for (int kt = 0; kt < T; ++kt) {
         // (a) diagonal tile, one wavefront, rows in registers: L_kk = chol(A_kk)
         // and its inverse X = L_kk^{-1} (row r of X is finished once the rows
-        // above it are, so rows are completed in order and broadcast by shuffles)
-        if (wave == 0) {
+        // above it are, so rows are completed in order and broadcast by shuffles).
+        // The wavefront taking this sequential step rotates with the tile column
+        // and the workgroup, so the co-resident workgroups of a CU spread it
+        // over the four SIMDs instead of queueing on one.
+        if (wave == ((kt + (int)blockIdx.x) & 3)) {
             double* Dt = tile_at(tiles, kt, kt);
             const int r = lane & 15;
             double row[16];
 #pragma unroll
             for (int c = 0; c < 16; ++c) row[c] = Dt[r * 16 + c];
             bool ok = true;
+            double rinv[16];   // 1 / L[q][q], the same on every lane
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const double dq = lane_bcast(row[q], q);
                 ok = ok && (dq > 0.0) && isfinite(dq);
                 const double lqq = sqrt(fmax(dq, 1e-300));
-                const double lrq = (r > q) ? row[q] / lqq : (r == q ? lqq : 0.0);
+                rinv[q] = 1.0 / lqq;
+                const double lrq = (r > q) ? row[q] * rinv[q] : (r == q ? lqq : 0.0);
                 row[q] = lrq;
 #pragma unroll
                 for (int j = q + 1; j < 16; ++j) {
@@ -238,7 +274,7 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
             for (int c = 0; c < 16; ++c) { acc[c] = 0.0; xr[c] = 0.0; }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const double dinv = 1.0 / lane_bcast(row[q], q);       // 1 / L[q][q]
+                const double dinv = rinv[q];
 #pragma unroll
                 for (int c = 0; c <= q; ++c) {
                     const double xq = ((q == c ? 1.0 : 0.0) - acc[c]) * dinv;   // X[q][c] on lane q
@@ -324,16 +360,35 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
         return;
     }
     // L^T Z = E (Z: 16T x 16, columns c < b carry the last b unit vectors),
-    // by tile rows: Z_I = X_II^T (E_I - sum_{J > I} L_JI^T Z_J) on MFMA
+    // by tile rows: Z_I = X_II^T (E_I - sum_{J > I} L_JI^T Z_J) on MFMA. Z is
+    // kept in LDS, in the space of the panel, which is free from here on.
+    double* Zs = panel;
     for (int I = T - 1; I >= 0; --I) {
-        v4d acc = {0.0, 0.0, 0.0, 0.0};
-        for (int J = I + 1 + wave; J < T; J += 4) {
-            const double* LJI = tile_at(tiles, J, I);
+        // the single-wavefront step of this tile row rotates like (a)
+        const bool own = wave == ((I + (int)blockIdx.x) & 3);
+        double xa[4];
+        if (own) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double av = LJI[(4 * q + (lane >> 4)) * 16 + (lane & 15)];          // L_JI^T
-                const double bv = Zl[(16 * J + 4 * q + (lane >> 4)) * 16 + (lane & 15)];  // Z_J
-                acc = mfma16(av, bv, acc);
+            for (int q = 0; q < 4; ++q) xa[q] = invs[I * 256 + (4 * q + (lane >> 4)) * 16 + (lane & 15)];   // X^T
+        }
+        v4d acc = {0.0, 0.0, 0.0, 0.0};
+        // wavefront w takes J = I + 1 + w + 4 s; four L_JI tiles are loaded before use
+        for (int J0 = I + 1 + wave; J0 < T; J0 += 16) {
+            double av[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double* LJI = tile_at(tiles, min(J0 + 4 * u, T - 1), I);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) av[u][q] = LJI[(4 * q + (lane >> 4)) * 16 + (lane & 15)];   // L_JI^T
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int J = J0 + 4 * u;
+                if (J < T) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc = mfma16(av[u][q], Zs[(16 * J + 4 * q + (lane >> 4)) * 16 + (lane & 15)], acc);   // Z_J
+                }
             }
         }
 #pragma unroll
@@ -346,17 +401,13 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
             part[1024 + e] = ev - (part[e] + part[256 + e] + part[512 + e] + part[768 + e]);
         }
         __syncthreads();
-        if (wave == 0) {
-            const double* XII = invs + I * 256;
+        if (own) {
             v4d z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double av = XII[(4 * q + (lane >> 4)) * 16 + (lane & 15)];          // X^T[row][4q+k]
-                const double bv = part[1024 + (4 * q + (lane >> 4)) * 16 + (lane & 15)];  // R[4q+k][col]
-                z = mfma16(av, bv, z);
-            }
+            for (int q = 0; q < 4; ++q)
+                z = mfma16(xa[q], part[1024 + (4 * q + (lane >> 4)) * 16 + (lane & 15)], z);   // R[4q+k][col]
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) Zl[(16 * I + 4 * rr + (lane >> 4)) * 16 + (lane & 15)] = z[rr];
+            for (int rr = 0; rr < 4; ++rr) Zs[(16 * I + 4 * rr + (lane >> 4)) * 16 + (lane & 15)] = z[rr];
         }
         __syncthreads();
     }
@@ -364,7 +415,7 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
         const int a = (int)(t / (b * b));
         const int rem = (int)(t - (int64_t)a * b * b);
         const int r = rem / b, c = rem - r * b;
-        g_vals[(p0 + a) * b * b + rem] = Zl[(a * b + c) * 16 + r];
+        g_vals[(p0 + a) * b * b + rem] = Zs[(a * b + c) * 16 + r];
     }
     __syncthreads();
 }
@@ -403,9 +454,9 @@ __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t*
             if (n > ntile && b <= 16) {
                 double* panel = lds;
                 double* part = panel + (int64_t)tmaxtiles * 256;
-                double* Zl = gK + (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256;   // global, after the tiles
-                double* invs = Zl + (int64_t)tmaxtiles * 256;                       // inverses of diagonal tiles
-                fsai_row_tiled(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, gK, panel, Zl, invs, part,
+                // inverses of the diagonal tiles: global, after the tiles
+                double* invs = gK + (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256;
+                fsai_row_tiled(k, b, a_rowptr, a_col, a_vals, p_rowptr, p_col, g_vals, gK, panel, invs, part,
                                idx, sh_flag, bad_row);
                 continue;
             }
@@ -455,7 +506,9 @@ static size_t lds_bytes(int nlds, int b) {
     return ((size_t)nlds * (nlds + 1) / 2 + (size_t)nlds * b) * sizeof(double);
 }
 
-static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s) {
+// Launches the persistent set-up kernel on s and returns without waiting;
+// `scratch` (the workgroups' global slots) must outlive the launch.
+static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s, DevBuf<double>& scratch) {
     const int cus = device_cu_count();
     const bool tiled = cfg.nt == 256 && a.b <= 16 && a.nmax > cfg.ntile;
     const int tmaxtiles = (a.nmax + 15) / 16;
@@ -471,9 +524,8 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s) {
     int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, std::max<int64_t>(1, a.nrows));
     int64_t stride = (int64_t)FSAI_MAXN * (FSAI_MAXN + 1) / 2 + (int64_t)FSAI_MAXN * a.b;
     if (tiled)
-        stride = std::max<int64_t>(stride, (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256 + 2 * (int64_t)tmaxtiles * 256);
+        stride = std::max<int64_t>(stride, (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256 + (int64_t)tmaxtiles * 256);
     // global scratch only when some row exceeds the LDS limit or is tiled
-    DevBuf<double> scratch;
     scratch.alloc(1);
     double* scr = scratch.p;
     if (a.nmax > nlds || tiled) {
@@ -497,7 +549,6 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s) {
         default: go(k_fsai_setup<256>, 256); break;
     }
     CHF_LAUNCH_CHECK();
-    CHF_HIP(hipStreamSynchronize(s));  // scratch is released on return
 }
 
 static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order_host, hipStream_t s) {
@@ -533,10 +584,13 @@ static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order
         smp.nrows = (int64_t)smp_order.size();
         smp.order = d_smp.p;
         double best_t = 1e30;
+        DevBuf<double> scratch;
         for (const TuneVal& c : cands) {
-            launch_setup(c, smp, s);  // warm-up
+            launch_setup(c, smp, s, scratch);  // warm-up
+            CHF_HIP(hipStreamSynchronize(s));
             auto t0 = std::chrono::steady_clock::now();
-            launch_setup(c, smp, s);
+            launch_setup(c, smp, s, scratch);
+            CHF_HIP(hipStreamSynchronize(s));
             double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             if (dt < best_t) { best_t = dt; best = c; }
         }
@@ -577,12 +631,17 @@ static void build_transpose_structure(const chf_fsai_s& G, std::vector<int64_t>&
         }
 }
 
-void fsai_build_layouts(chf_fsai_s& G, hipStream_t s) {
+// SpMV layouts of G and G^T: their structure depends on the pattern only
+// (host work), the packing of the values needs the factor (device work).
+static void fsai_plan_layouts(chf_fsai_s& G) {
     G.plan_g = sell_plan(G.nb, G.b, G.rowptr, G.colidx, nullptr);
     std::vector<int64_t> trow, tsrc;
     std::vector<int32_t> tcol;
     build_transpose_structure(G, trow, tcol, tsrc);
     G.plan_gt = sell_plan(G.nb, G.b, trow, tcol, &tsrc);
+}
+
+static void fsai_pack_layouts(chf_fsai_s& G, hipStream_t s) {
     sell_build(G.g64, G.plan_g, G.d_vals.p, false, CHF_F64, s);
     sell_build(G.gt64, G.plan_gt, G.d_vals.p, true, CHF_F64, s);
     if (G.store != CHF_F64) {
@@ -644,7 +703,15 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
         SetupArgs args{nb, d_order.p, b, A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, d_prow.p, d_pcol.p,
                        G->d_vals.p, std::min(max_lds_n(b), nmax), d_flags.p, d_flags.p + 1, nmax};
         TuneVal cfg = pick_config(args, order, s);
-        launch_setup(cfg, args, s);
+        DevBuf<double> scratch;
+        launch_setup(cfg, args, s, scratch);
+        // the host plans the layouts while the factorisation runs
+        try {
+            fsai_plan_layouts(*G);
+        } catch (...) {
+            (void)hipStreamSynchronize(s);   // the kernel still reads buffers freed on unwinding
+            throw;
+        }
         int flags[2];
         d_flags.download(flags, 2, s);
         CHF_HIP(hipStreamSynchronize(s));
@@ -654,7 +721,8 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
                                   " is not positive definite");
         }
     }
-    fsai_build_layouts(*G, s);
+    if (nb == 0) fsai_plan_layouts(*G);
+    fsai_pack_layouts(*G, s);
     CHF_HIP(hipStreamSynchronize(s));
     return G.release();
 }
