@@ -110,23 +110,29 @@ __global__ void k_basis_t(int64_t nb, int b, const TV* __restrict__ T, const TV*
     y[t] = acc;
 }
 
-// x_i += T_i z_i with z_i = sum_{(I, w) in P(i)} w x_c[I]
+// x_i += T_i z_i with z_i = sum_{(I, w) in P(i)} w x_c[I]. A wavefront holds
+// S = 64 / b block rows, lane = local_row * b + r: the lane forms component r
+// of z_i once, and the row's b lanes exchange their components by shuffles.
 template <typename TV>
 __global__ void k_prolong_add_basis(int64_t nf, int b, const int64_t* __restrict__ p_rowptr,
                                     const int* __restrict__ p_col, const double* __restrict__ p_val,
                                     const TV* __restrict__ T, const TV* __restrict__ xc, TV* __restrict__ x) {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= nf * b) return;
-    const int64_t i = t / b;
-    const int r = (int)(t - i * b);
+    const int S = 64 / b;
+    const int lane = threadIdx.x & 63;
+    const int64_t wv = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int lr = lane / b, r = lane - lr * b;
+    const int64_t i = wv * S + lr;
+    const bool active = lr < S && i < nf;
+    TV z = 0;
+    if (active)
+        for (int64_t e = p_rowptr[i]; e < p_rowptr[i + 1]; ++e) z += (TV)p_val[e] * xc[(int64_t)p_col[e] * b + r];
     const TV* Ti = T + i * b * b + r * b;
     TV acc = 0;
     for (int c = 0; c < b; ++c) {
-        TV z = 0;
-        for (int64_t e = p_rowptr[i]; e < p_rowptr[i + 1]; ++e) z += (TV)p_val[e] * xc[(int64_t)p_col[e] * b + c];
-        acc += Ti[c] * z;
+        const TV zc = __shfl(z, lr * b + c, 64);   // lanes past S * b read a wrapped lane, unused
+        if (active) acc += Ti[c] * zc;
     }
-    x[t] += acc;
+    if (active) x[i * b + r] += acc;
 }
 
 // ------------------------------------------------------------- transfers --
@@ -487,11 +493,13 @@ static void prolong_add(chf_levels_s& H, int l, const void* xc, void* x, hipStre
     int64_t tot = nf * b;
     dim3 grid((unsigned)((tot + 255) / 256));
     if (L.has_T) {
+        const int64_t waves = (nf + 64 / b - 1) / (64 / b);
+        dim3 gw((unsigned)((waves + 3) / 4));   // four wavefronts per 256-wide workgroup
         if (H.vec == CHF_F64)
-            hipLaunchKernelGGL((k_prolong_add_basis<double>), grid, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
+            hipLaunchKernelGGL((k_prolong_add_basis<double>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
                                L.d_p_col.p, L.d_p_val.p, (const double*)L.d_T64.p, (const double*)xc, (double*)x);
         else
-            hipLaunchKernelGGL((k_prolong_add_basis<float>), grid, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
+            hipLaunchKernelGGL((k_prolong_add_basis<float>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
                                L.d_p_col.p, L.d_p_val.p, (const float*)L.d_T32.p, (const float*)xc, (float*)x);
         CHF_LAUNCH_CHECK();
         return;

@@ -37,7 +37,9 @@ def test_galerkin_operators(chf, n, b, levels):
         assert rel_err(vals, oa.vals) < 1e-13
 
 
-@pytest.mark.parametrize("n,b,levels,degree", [(16, 3, 3, 2), (32, 10, 3, 3)])
+# b = 1 puts 64 block rows in a wavefront of the basis prolongation, b = 7 leaves
+# one lane idle
+@pytest.mark.parametrize("n,b,levels,degree", [(16, 3, 3, 2), (32, 10, 3, 3), (16, 1, 3, 2), (16, 7, 3, 2)])
 def test_vcycle_matches_oracle(chf, n, b, levels, degree):
     import torch
     p = make_problem(n, 2, b, 2, seed=0)
