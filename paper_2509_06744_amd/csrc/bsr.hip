@@ -238,60 +238,54 @@ __device__ inline int64_t xcd_slice_block(int64_t nwork_blocks) {
     return (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
-template <int BT, int V, typename TA, typename TV, int EPI, bool NTL>
-__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, int brt,
-                                                   const int* __restrict__ soff, const int* __restrict__ cols,
-                                                   const TA* __restrict__ vals, const TV* __restrict__ x,
-                                                   TV* __restrict__ y, const TV* __restrict__ bv,
-                                                   TV* __restrict__ p, TV* __restrict__ xo, TV alpha, TV beta) {
-    const int b = BT ? BT : brt;
-    const int S = 64 / b;
-    const int L = S * b;
-    const int64_t slice = xcd_slice_block((nslices + 3) / 4) * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (slice >= nslices || lane >= L) return;
-    const int lr = lane / b;
-    const int r = lane - lr * b;
-    const int64_t row = slice * S + lr;
-    if (row >= nb) return;
-    const int j0 = soff[slice], j1 = soff[slice + 1];
+// Sum over the slots j = j_first, j_first + STEP, ... < j1 of one lane's row r
+// of its block row: sum_c block_j[r][c] x[col_j b + c].
+template <int BT, int V, typename TA, typename TV, bool NTL, int STEP>
+__device__ inline TV sell_lane_sum(int b, int S, int L, int lane, int lr, int j_first, int j1,
+                                   const int* __restrict__ cols, const TA* __restrict__ vals,
+                                   const TV* __restrict__ x) {
     TV acc = 0;
     if constexpr (BT == 10 && V == 4) {
         // runs of 4, 4 and 2 columns per slot (16-, 16- and 8-byte loads)
         const int64_t stride = (int64_t)10 * L;
-        const TA* v = vals + (int64_t)j0 * stride;
-        const int* cp = cols + (int64_t)j0 * S + lr;
+        const TA* v = vals + (int64_t)j_first * stride;
+        const int* cp = cols + (int64_t)j_first * S + lr;
 #pragma unroll 2
-        for (int j = j0; j < j1; ++j) {
+        for (int j = j_first; j < j1; j += STEP) {
             const TV* xc = x + (int64_t)(*cp) * 10;
             acc += Pair<4, TA, TV, NTL>::dot(v + lane * 4, xc);
             acc += Pair<4, TA, TV, NTL>::dot(v + 4 * L + lane * 4, xc + 4);
             acc += Pair<2, TA, TV, NTL>::dot(v + 8 * L + lane * 2, xc + 8);
-            v += stride;
-            cp += S;
+            v += STEP * stride;
+            cp += STEP * S;
         }
     } else if constexpr (BT > 0) {
         constexpr int NQ = BT / V;
         const int64_t stride = (int64_t)NQ * L * V;
-        const TA* v = vals + (int64_t)j0 * stride + lane * V;
-        const int* cp = cols + (int64_t)j0 * S + lr;
+        const TA* v = vals + (int64_t)j_first * stride + lane * V;
+        const int* cp = cols + (int64_t)j_first * S + lr;
 #pragma unroll 2
-        for (int j = j0; j < j1; ++j) {
+        for (int j = j_first; j < j1; j += STEP) {
             const TV* xc = x + (int64_t)(*cp) * BT;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) acc += Pair<V, TA, TV, NTL>::dot(v + q * L * V, xc + q * V);
-            v += stride;
-            cp += S;
+            v += STEP * stride;
+            cp += STEP * S;
         }
     } else {
-        for (int j = j0; j < j1; ++j) {
+        for (int j = j_first; j < j1; j += STEP) {
             const int col = cols[(int64_t)j * S + lr];
             const TA* v = vals + (int64_t)j * b * L + lane;
             const TV* xc = x + (int64_t)col * b;
             for (int c = 0; c < b; ++c) acc += Pair<1, TA, TV, NTL>::dot(v + c * L, xc + c);
         }
     }
-    const int64_t o = row * b + r;
+    return acc;
+}
+
+template <int EPI, typename TV>
+__device__ inline void sell_epilogue(int64_t o, TV acc, TV* __restrict__ y, const TV* __restrict__ bv,
+                                     TV* __restrict__ p, TV* __restrict__ xo, TV alpha, TV beta) {
     if constexpr (EPI == EPI_AX) {
         y[o] = acc;
     } else if constexpr (EPI == EPI_RES) {
@@ -309,17 +303,86 @@ __global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, 
     }
 }
 
+template <int BT, int V, typename TA, typename TV, int EPI, bool NTL>
+__global__ __launch_bounds__(256) void k_sell_spmv(int64_t nslices, int64_t nb, int brt,
+                                                   const int* __restrict__ soff, const int* __restrict__ cols,
+                                                   const TA* __restrict__ vals, const TV* __restrict__ x,
+                                                   TV* __restrict__ y, const TV* __restrict__ bv,
+                                                   TV* __restrict__ p, TV* __restrict__ xo, TV alpha, TV beta) {
+    const int b = BT ? BT : brt;
+    const int S = 64 / b;
+    const int L = S * b;
+    const int64_t slice = xcd_slice_block((nslices + 3) / 4) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slice >= nslices || lane >= L) return;
+    const int lr = lane / b;
+    const int r = lane - lr * b;
+    const int64_t row = slice * S + lr;
+    if (row >= nb) return;
+    const TV acc = sell_lane_sum<BT, V, TA, TV, NTL, 1>(b, S, L, lane, lr, soff[slice], soff[slice + 1], cols, vals, x);
+    sell_epilogue<EPI>(row * b + r, acc, y, bv, p, xo, alpha, beta);
+}
+
+// Small matrices (few slices, so too few wavefronts to cover the latency of
+// their slots): one workgroup per slice, wavefront w takes the slots
+// j0 + w, j0 + w + 4, ..., and the four partial sums meet in LDS.
+template <int BT, int V, typename TA, typename TV, int EPI, bool NTL>
+__global__ __launch_bounds__(256) void k_sell_spmv_split(int64_t nslices, int64_t nb, int brt,
+                                                         const int* __restrict__ soff, const int* __restrict__ cols,
+                                                         const TA* __restrict__ vals, const TV* __restrict__ x,
+                                                         TV* __restrict__ y, const TV* __restrict__ bv,
+                                                         TV* __restrict__ p, TV* __restrict__ xo, TV alpha, TV beta) {
+    __shared__ TV part[3][64];
+    const int b = BT ? BT : brt;
+    const int S = 64 / b;
+    const int L = S * b;
+    const int64_t slice = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane / b;
+    const int r = lane - lr * b;
+    const int64_t row = slice * S + lr;
+    const bool act = slice < nslices && lane < L && row < nb;
+    TV acc = 0;
+    if (act)
+        acc = sell_lane_sum<BT, V, TA, TV, NTL, 4>(b, S, L, lane, lr, soff[slice] + w, soff[slice + 1], cols, vals, x);
+    if (w > 0) part[w - 1][lane] = acc;
+    __syncthreads();
+    if (w == 0 && act) {
+        acc += (part[0][lane] + part[1][lane]) + part[2][lane];
+        sell_epilogue<EPI>(row * b + r, acc, y, bv, p, xo, alpha, beta);
+    }
+}
+
+// Matrices with fewer slices than this use the split kernel (one workgroup per
+// slice); CHF_SPMV_SPLIT_BELOW overrides it (0: never split).
+static int64_t spmv_split_below() {
+    const char* e = std::getenv("CHF_SPMV_SPLIT_BELOW");
+    return e ? std::atoll(e) : 2048;
+}
+
 template <int BT, int V, typename TA, typename TV>
 static void launch_spmv_t(const Sell& A, const void* x, void* y, const void* bv, int epi, void* p, void* xo,
                           double alpha, double beta, hipStream_t s) {
     const int64_t nblk = (A.nslices + 3) / 4;
     if (nblk == 0) return;
-    dim3 grid((unsigned)((nblk + 7) / 8 * 8)), block(256);
+    const bool split = A.nslices < spmv_split_below();
+    dim3 grid(split ? (unsigned)A.nslices : (unsigned)((nblk + 7) / 8 * 8)), block(256);
     auto args = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, block, 0, s, A.nslices, A.nb, A.b, A.slice_off.p, A.cols.p,
                            (const TA*)A.vals.p, (const TV*)x, (TV*)y, (const TV*)bv, (TV*)p, (TV*)xo, (TV)alpha,
                            (TV)beta);
     };
+    if (split) {
+        switch (epi) {
+            case EPI_AX: args(k_sell_spmv_split<BT, V, TA, TV, EPI_AX, true>); break;
+            case EPI_RES: args(k_sell_spmv_split<BT, V, TA, TV, EPI_RES, true>); break;
+            case EPI_CHEB_FIRST0: args(k_sell_spmv_split<BT, V, TA, TV, EPI_CHEB_FIRST0, true>); break;
+            case EPI_CHEB_FIRST: args(k_sell_spmv_split<BT, V, TA, TV, EPI_CHEB_FIRST, true>); break;
+            default: args(k_sell_spmv_split<BT, V, TA, TV, EPI_CHEB, true>); break;
+        }
+        CHF_LAUNCH_CHECK();
+        return;
+    }
     // non-temporal matrix loads are the default (measured at 512^2, b = 10:
     // residual SpMV 78 % instead of 71 % of HBM peak); CHF_SPMV_NONTEMPORAL=0
     // turns them off

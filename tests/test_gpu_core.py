@@ -24,8 +24,16 @@ def chf():
     return m
 
 
+# CHF_SPMV_SPLIT_BELOW: "0" keeps every matrix on the one-wavefront-per-slice
+# kernel, "1000000000" sends every matrix to the split kernel (one workgroup
+# per slice), so both SpMV kernels are checked at every size
+SPLIT = ["0", "1000000000"]
+
+
 @pytest.mark.parametrize("n,dim,b,pw", CASES)
-def test_bsr_roundtrip_and_spmv(chf, n, dim, b, pw):
+@pytest.mark.parametrize("split_below", SPLIT)
+def test_bsr_roundtrip_and_spmv(chf, n, dim, b, pw, split_below, monkeypatch):
+    monkeypatch.setenv("CHF_SPMV_SPLIT_BELOW", split_below)
     p = make_problem(n, dim, b, pw, seed=1)
     A = upload(p)
     rp, ci, vals = chf.bsr_export(A)
@@ -83,8 +91,10 @@ def test_fsai_full_pattern_and_diagonal(chf):
 @pytest.mark.parametrize("n,dim,b,pw", CASES[1:])
 @pytest.mark.parametrize("degree", [1, 3, 4])
 @pytest.mark.parametrize("x_is_zero", [False, True])
-def test_cheb4_smoother(chf, n, dim, b, pw, degree, x_is_zero):
+@pytest.mark.parametrize("split_below", SPLIT)
+def test_cheb4_smoother(chf, n, dim, b, pw, degree, x_is_zero, split_below, monkeypatch):
     import torch
+    monkeypatch.setenv("CHF_SPMV_SPLIT_BELOW", split_below)
     p = make_problem(n, dim, b, pw, seed=0)
     a = from_problem(p)
     og = fsai.fsai(a, *fsai.pattern_lower(a))
