@@ -4,8 +4,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 
+#include <functional>
 #include <memory>
+#include <thread>
 
 #include "internal.h"
 #include "kernels_common.h"
@@ -25,6 +28,60 @@ void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const
                   double* beta_out, double* theta_out, hipStream_t s);
 chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_t s);
 void validate_pattern(int64_t nb, const int64_t* rowptr, const int32_t* colidx);
+
+// ------------------------------------------------- host structure products --
+// Runs f(c) for c = 0 .. ntask-1, one host thread per task.
+// The first exception a task throws is rethrown here after all have joined.
+static void run_tasks(int ntask, const std::function<void(int)>& f) {
+    if (ntask <= 1) {
+        if (ntask == 1) f(0);
+        return;
+    }
+    std::vector<std::exception_ptr> err(ntask);
+    std::vector<std::thread> th;
+    for (int c = 0; c < ntask; ++c)
+        th.emplace_back([&, c] {
+            try {
+                f(c);
+            } catch (...) {
+                err[c] = std::current_exception();
+            }
+        });
+    for (auto& x : th) x.join();
+    for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+}
+
+// Structure of the product X Y of two CSR patterns (X: nr rows, Y: columns
+// < ncol): row r = the sorted union of the rows Y(k), k in X(r).
+static void struct_product(int64_t nr, const int64_t* xr, const int32_t* xc, const int64_t* yr, const int32_t* yc,
+                           int64_t ncol, std::vector<int64_t>& orow, std::vector<int32_t>& ocol) {
+    const int64_t hw = std::max<unsigned>(1u, std::thread::hardware_concurrency());
+    const int nchunk = (int)std::min<int64_t>(std::min<int64_t>(hw, 16), std::max<int64_t>(1, nr / 2048));
+    std::vector<std::vector<int32_t>> cols(nchunk);
+    std::vector<int64_t> len(nr + 1, 0);
+    run_tasks(nchunk, [&](int c) {
+        std::vector<int32_t> mark((size_t)ncol, -1), tmp;
+        const int64_t lo = nr * c / nchunk, hi = nr * (c + 1) / nchunk;
+        for (int64_t r = lo; r < hi; ++r) {
+            tmp.clear();
+            for (int64_t e = xr[r]; e < xr[r + 1]; ++e) {
+                const int64_t k = xc[e];
+                for (int64_t f = yr[k]; f < yr[k + 1]; ++f) {
+                    const int32_t j = yc[f];
+                    if (mark[j] != (int32_t)r) { mark[j] = (int32_t)r; tmp.push_back(j); }
+                }
+            }
+            std::sort(tmp.begin(), tmp.end());
+            cols[c].insert(cols[c].end(), tmp.begin(), tmp.end());
+            len[r + 1] = (int64_t)tmp.size();
+        }
+    });
+    orow.assign(nr + 1, 0);
+    for (int64_t r = 0; r < nr; ++r) orow[r + 1] = orow[r] + len[r + 1];
+    ocol.resize((size_t)orow[nr]);
+    run_tasks(nchunk, [&](int c) { std::copy(cols[c].begin(), cols[c].end(), ocol.begin() + orow[nr * c / nchunk]); });
+}
 
 // ------------------------------------------------------------- Galerkin --
 // A_c[I, J] = sum_{i in P^T(I)} sum_{j in A(i)} sum_{J in P(j)} P_iI A_ij P_jJ.
@@ -650,26 +707,11 @@ extern "C" int chf_levels_add_coarse(chf_levels H, int64_t nc, const int64_t* p_
                 F.pt_col[pos] = (int32_t)i;
                 F.pt_val[pos] = F.p_val[e];
             }
-        // coarse structure: union over i in P^T(I), j in A(i), J in P(j)
-        std::vector<int64_t> crow(nc + 1, 0);
-        std::vector<int32_t> ccol;
-        std::vector<int32_t> mark(nc, -1), tmp;
-        for (int64_t I = 0; I < nc; ++I) {
-            tmp.clear();
-            for (int64_t ti = F.pt_rowptr[I]; ti < F.pt_rowptr[I + 1]; ++ti) {
-                int64_t i = F.pt_col[ti];
-                for (int64_t ea = A->rowptr[i]; ea < A->rowptr[i + 1]; ++ea) {
-                    int64_t j = A->colidx[ea];
-                    for (int64_t tj = F.p_rowptr[j]; tj < F.p_rowptr[j + 1]; ++tj) {
-                        int32_t J = F.p_col[tj];
-                        if (mark[J] != I) { mark[J] = (int32_t)I; tmp.push_back(J); }
-                    }
-                }
-            }
-            std::sort(tmp.begin(), tmp.end());
-            ccol.insert(ccol.end(), tmp.begin(), tmp.end());
-            crow[I + 1] = (int64_t)ccol.size();
-        }
+        // coarse structure struct(P^T A P) = struct(P^T T) with T = struct(A P)
+        std::vector<int64_t> trow, crow;
+        std::vector<int32_t> tcol, ccol;
+        struct_product(nf, A->rowptr.data(), A->colidx.data(), F.p_rowptr.data(), F.p_col.data(), nc, trow, tcol);
+        struct_product(nc, F.pt_rowptr.data(), F.pt_col.data(), trow.data(), tcol.data(), nc, crow, ccol);
         hipStream_t s = 0;
         auto up64 = [&](DevBuf<int64_t>& d, const std::vector<int64_t>& h) {
             d.alloc(std::max<size_t>(1, h.size())); d.upload(h.data(), h.size(), s); };
@@ -693,14 +735,18 @@ extern "C" int chf_levels_add_coarse(chf_levels H, int64_t nc, const int64_t* p_
         DevBuf<double> tvals;
         if (basis) {
             const size_t nt = (size_t)nf * b * b;
-            for (size_t q = 0; q < nt; ++q)
-                CHF_CHECK(std::isfinite(basis[q]), CHF_EINVAL, "non-finite basis value");
+            const int nchunk = (int)std::min<size_t>(16, std::max<size_t>(1, nt >> 20));
+            std::vector<char> bad(nchunk, 0);
+            run_tasks(nchunk, [&](int c) {
+                for (size_t q = nt * c / nchunk, q1 = nt * (c + 1) / nchunk; q < q1; ++q)
+                    if (!std::isfinite(basis[q])) { bad[c] = 1; break; }
+            });
+            for (char f : bad) CHF_CHECK(!f, CHF_EINVAL, "non-finite basis value");
             F.has_T = true;
             F.d_T64.alloc(nt);
             F.d_T64.upload(basis, nt, s);
-            std::vector<float> t32(basis, basis + nt);
             F.d_T32.alloc(nt);
-            F.d_T32.upload(t32.data(), nt, s);
+            cast_vec(CHF_F64, F.d_T64.p, CHF_F32, F.d_T32.p, (int64_t)nt, s);
             tvals.alloc(std::max<int64_t>(1, A->nnzb * b * b));
             int ntc = std::min(256, ((b * b + 63) / 64) * 64);
             hipLaunchKernelGGL(k_congruence, dim3((unsigned)nf), dim3(ntc), (size_t)b * b * 8, s, nf, b, A->d_rowptr.p,
