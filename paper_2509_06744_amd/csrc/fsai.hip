@@ -160,6 +160,57 @@ __device__ inline void tri_decode(int t, int& I, int& J) {
     J = t - i * (i + 1) / 2;
 }
 
+// One wavefront: Cholesky factor L of the 16 x 16 SPD tile Dt (row-major; lane
+// l works on row l % 16 in registers) and its inverse X = L^{-1}, written to X
+// and to inv. Row r of X is finished once the rows above it are, so rows
+// complete in order and are broadcast by readlane. Returns false if a pivot is
+// not positive and finite.
+__device__ inline bool diag_tile_inv(const double* Dt, double* X, double* inv, int lane) {
+    const int r = lane & 15;
+    double row[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) row[c] = Dt[r * 16 + c];
+    bool ok = true;
+    double rinv[16];   // 1 / L[q][q], the same on every lane
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const double dq = lane_bcast(row[q], q);
+        ok = ok && (dq > 0.0) && isfinite(dq);
+        const double lqq = sqrt(fmax(dq, 1e-300));
+        rinv[q] = 1.0 / lqq;
+        const double lrq = (r > q) ? row[q] * rinv[q] : (r == q ? lqq : 0.0);
+        row[q] = lrq;
+#pragma unroll
+        for (int j = q + 1; j < 16; ++j) {
+            const double ljq = lane_bcast(lrq, j);
+            if (j <= r) row[j] -= lrq * ljq;
+        }
+    }
+    double acc[16], xr[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) { acc[c] = 0.0; xr[c] = 0.0; }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const double dinv = rinv[q];
+#pragma unroll
+        for (int c = 0; c <= q; ++c) {
+            const double xq = ((q == c ? 1.0 : 0.0) - acc[c]) * dinv;   // X[q][c] on lane q
+            const double v = lane_bcast(xq, q);
+            if (r == q) xr[c] = v;
+            if (r > q) acc[c] += row[q] * v;
+        }
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const double v = c <= r ? xr[c] : 0.0;
+            X[r * 16 + c] = v;
+            inv[r * 16 + c] = v;
+        }
+    }
+    return ok;
+}
+
 __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                const double* __restrict__ a_vals, const int64_t* __restrict__ p_rowptr,
                                const int* __restrict__ p_col, double* __restrict__ g_vals, double* tiles,
@@ -240,108 +291,96 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
     }
     if (tid == 0) sh_flag[0] = 1;
     __syncthreads();
-    for (int kt = 0; kt < T; ++kt) {
-        // (a) diagonal tile, one wavefront, rows in registers: L_kk = chol(A_kk)
-        // and its inverse X = L_kk^{-1} (row r of X is finished once the rows
-        // above it are, so rows are completed in order and broadcast by shuffles).
-        // The wavefront taking this sequential step rotates with the tile column
-        // and the workgroup, so the co-resident workgroups of a CU spread it
-        // over the four SIMDs instead of queueing on one.
-        if (wave == ((kt + (int)blockIdx.x) & 3)) {
-            double* Dt = tile_at(tiles, kt, kt);
-            const int r = lane & 15;
-            double row[16];
+    // Right-looking by pairs of tile columns k, k + 1, so that each trailing
+    // tile is read and written once per two columns:
+    //   (a) one wavefront factors A_kk and inverts the factor, X = L_kk^{-1};
+    //   (b) L_ik = A_ik X^T (i > k) to the slot and to LDS;
+    //   (c1) column k + 1 alone: A_{i,k+1} -= L_ik L_{k+1,k}^T (i > k);
+    //   (a2), (b2) the same two steps for column k + 1 (panel to the slot only);
+    //   (c) A_IJ -= L_Ik L_Jk^T + L_{I,k+1} L_{J,k+1}^T (J, I > k + 1), with
+    //       column k from LDS and column k + 1 read back through L2.
+    // The wavefront taking the sequential step rotates with the column and the
+    // workgroup, spreading it over the SIMDs.
+    for (int kt = 0; kt < T; kt += 2) {
+        for (int h = 0; h < 2 && kt + h < T; ++h) {
+            const int kc = kt + h;   // the column factored in this step: (a), (b) for h = 0; (a2), (b2) for h = 1
+            if (wave == ((kc + (int)blockIdx.x) & 3)) {
+                if (!diag_tile_inv(tile_at(tiles, kc, kc), panel, invs + kc * 256, lane) && lane == 0) sh_flag[0] = 0;
+            }
+            __syncthreads();
+            if (!sh_flag[0]) break;
+            // L_ic = A_ic X^T: step q takes A_ic[l % 16][4q + l / 16] and
+            // X^T[4q + l / 16][l % 16] = X[l % 16][4q + l / 16]; column k also to LDS
+            for (int ti = kc + 1 + wave; ti < T; ti += 4) {
+                double* Tt = tile_at(tiles, ti, kc);
+                v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < 16; ++c) row[c] = Dt[r * 16 + c];
-            bool ok = true;
-            double rinv[16];   // 1 / L[q][q], the same on every lane
+                for (int q = 0; q < 4; ++q)
+                    acc = mfma16(Tt[(lane & 15) * 16 + 4 * q + (lane >> 4)], panel[(lane & 15) * 16 + 4 * q + (lane >> 4)],
+                                 acc);
+                double* pt = panel + (ti - kt) * 256;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const double dq = lane_bcast(row[q], q);
-                ok = ok && (dq > 0.0) && isfinite(dq);
-                const double lqq = sqrt(fmax(dq, 1e-300));
-                rinv[q] = 1.0 / lqq;
-                const double lrq = (r > q) ? row[q] * rinv[q] : (r == q ? lqq : 0.0);
-                row[q] = lrq;
-#pragma unroll
-                for (int j = q + 1; j < 16; ++j) {
-                    const double ljq = lane_bcast(lrq, j);
-                    if (j <= r) row[j] -= lrq * ljq;
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int o = (4 * rr + (lane >> 4)) * 16 + (lane & 15);
+                    Tt[o] = acc[rr];
+                    if (h == 0) pt[o] = acc[rr];
                 }
             }
-            double acc[16], xr[16];
+            __syncthreads();
+            if (h == 0) {
+                // (c1) column k + 1 alone: A_{i,k+1} -= L_ik L_{k+1,k}^T, L_{k+1,k} in LDS slot 1
+                for (int ti = kt + 1 + wave; ti < T; ti += 4) {
+                    double* Ct = tile_at(tiles, ti, kt + 1);
+                    v4d acc;
 #pragma unroll
-            for (int c = 0; c < 16; ++c) { acc[c] = 0.0; xr[c] = 0.0; }
+                    for (int rr = 0; rr < 4; ++rr) acc[rr] = Ct[(4 * rr + (lane >> 4)) * 16 + (lane & 15)];
+                    const double* Li = panel + (ti - kt) * 256;
+                    const double* Lj = panel + 256;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const double dinv = rinv[q];
+                    for (int q = 0; q < 4; ++q)
+                        acc = mfma16(-Li[(lane & 15) * 16 + 4 * q + (lane >> 4)], Lj[(lane & 15) * 16 + 4 * q + (lane >> 4)],
+                                     acc);
 #pragma unroll
-                for (int c = 0; c <= q; ++c) {
-                    const double xq = ((q == c ? 1.0 : 0.0) - acc[c]) * dinv;   // X[q][c] on lane q
-                    const double v = lane_bcast(xq, q);
-                    if (r == q) xr[c] = v;
-                    if (r > q) acc[c] += row[q] * v;
+                    for (int rr = 0; rr < 4; ++rr) Ct[(4 * rr + (lane >> 4)) * 16 + (lane & 15)] = acc[rr];
                 }
-            }
-            if (lane < 16) {
-                double* inv = invs + kt * 256;
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    const double v = c <= r ? xr[c] : 0.0;
-                    panel[r * 16 + c] = v;
-                    inv[r * 16 + c] = v;
-                }
-            }
-            if (lane == 0 && !ok) sh_flag[0] = 0;
-        }
-        __syncthreads();
-        if (!sh_flag[0]) break;
-        // (b) panel: L_ik = A_ik L_kk^{-T} = A_ik X^T on MFMA, one tile per wavefront
-        for (int ti = kt + 1 + wave; ti < T; ti += 4) {
-            double* Tt = tile_at(tiles, ti, kt);
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double av = Tt[(lane & 15) * 16 + 4 * q + (lane >> 4)];          // A_ik[row][4q+k]
-                const double bv = panel[(lane & 15) * 16 + 4 * q + (lane >> 4)];       // X^T[4q+k][col] = X[col][4q+k]
-                acc = mfma16(av, bv, acc);
-            }
-            double* pt = panel + (ti - kt) * 256;
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int o = (4 * rr + (lane >> 4)) * 16 + (lane & 15);
-                Tt[o] = acc[rr];
-                pt[o] = acc[rr];
+                __syncthreads();
             }
         }
-        __syncthreads();
-        // (c) trailing tiles A_IJ -= L_Ik L_Jk^T, kt < J <= I < T, on MFMA;
-        // each wavefront keeps four tiles in flight
-        const int nt = T - kt - 1;
+        if (!sh_flag[0] || kt + 1 >= T) break;
+        // (c) trailing tiles, k + 1 < J <= I < T; each wavefront keeps U tiles in flight
+        const int nt = T - kt - 2;
         const int npairs = nt * (nt + 1) / 2;
-        constexpr int U = 4;
+        constexpr int U = 2;
         for (int base = wave * U; base < npairs; base += 4 * U) {
             v4d acc[U];
+            double li2[U][4], lj2[U][4];
             double* Ct[U];
             int ii[U], jj[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int pidx = min(base + u, npairs - 1);
                 tri_decode(pidx, ii[u], jj[u]);
-                Ct[u] = tile_at(tiles, kt + 1 + ii[u], kt + 1 + jj[u]);
+                Ct[u] = tile_at(tiles, kt + 2 + ii[u], kt + 2 + jj[u]);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) acc[u][rr] = Ct[u][(4 * rr + (lane >> 4)) * 16 + (lane & 15)];
+                const double* Li2 = tile_at(tiles, kt + 2 + ii[u], kt + 1);
+                const double* Lj2 = tile_at(tiles, kt + 2 + jj[u], kt + 1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    li2[u][q] = Li2[(lane & 15) * 16 + 4 * q + (lane >> 4)];
+                    lj2[u][q] = Lj2[(lane & 15) * 16 + 4 * q + (lane >> 4)];
+                }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double* Li = panel + (ii[u] + 1) * 256;
-                const double* Lj = panel + (jj[u] + 1) * 256;
+                const double* Li = panel + (ii[u] + 2) * 256;   // L_{I,k}: LDS slot I - k
+                const double* Lj = panel + (jj[u] + 2) * 256;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double av = -Li[(lane & 15) * 16 + 4 * q + (lane >> 4)];
-                    const double bv = Lj[(lane & 15) * 16 + 4 * q + (lane >> 4)];
-                    acc[u] = mfma16(av, bv, acc[u]);
-                }
+                for (int q = 0; q < 4; ++q)
+                    acc[u] = mfma16(-Li[(lane & 15) * 16 + 4 * q + (lane >> 4)], Lj[(lane & 15) * 16 + 4 * q + (lane >> 4)],
+                                    acc[u]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[u] = mfma16(-li2[u][q], lj2[u][q], acc[u]);
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
