@@ -131,10 +131,19 @@ def test_lanczos_bound(chf):
     assert beta >= np.linalg.eigvalsh(bm).max()
 
 
-def test_error_not_spd_reports_row(chf):
-    p = make_problem(6, 2, 3, 2, seed=0)
+# Negating A_kk makes the local system of row k indefinite, first at block k's
+# first pivot; rows below k do not contain block k, so k is the reported row.
+# With '256,1' every row goes through the tiled solver, which factors pairs of
+# tile columns: at b = 10 the failing pivot of row 1 (row 10 of a 20-wide
+# system) lies in tile column 0, the first of a pair, and that of row 17 (row
+# 50 of a 60-wide system) in tile column 3, the second of a pair.
+@pytest.mark.parametrize("b,k", [(3, 17), (10, 1), (10, 17)])
+@pytest.mark.parametrize("config", [None, "256,1"])
+def test_error_not_spd_reports_row(chf, b, k, config, monkeypatch):
+    if config:
+        monkeypatch.setenv("CHF_FSAI_CONFIG", config)
+    p = make_problem(6, 2, b, 2, seed=0)
     vals = p.vals.copy()
-    k = 17
     e = p.rowptr[k] + np.searchsorted(p.colidx[p.rowptr[k]:p.rowptr[k + 1]], k)
     vals[e] = -vals[e]
     A = chf.bsr_create(p.nb, p.b, p.rowptr, p.colidx, vals)
