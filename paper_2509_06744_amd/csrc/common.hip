@@ -8,6 +8,17 @@
 namespace chf {
 
 static thread_local std::string g_last_error;
+static thread_local std::vector<void*>* g_free_deferral = nullptr;
+
+void set_free_deferral(std::vector<void*>* list) { g_free_deferral = list; }
+
+void dev_free(void* p) {
+    if (!p) return;
+    if (g_free_deferral)
+        g_free_deferral->push_back(p);
+    else
+        (void)hipFree(p);
+}
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 

@@ -57,6 +57,12 @@ int guarded(F&& f) {
 }
 
 // ------------------------------------------------------------ device mem --
+// Frees device memory, or, while the calling thread has a deferral list set,
+// records the pointer for the caller to free later. hipFree synchronises the
+// whole device, so a free would serialise work overlapped on two streams.
+void dev_free(void* p);
+void set_free_deferral(std::vector<void*>* list);   // nullptr: free at once
+
 template <class T>
 struct DevBuf {
     T* p = nullptr;
@@ -77,7 +83,7 @@ struct DevBuf {
         if (count) CHF_HIP(hipMalloc(&p, count * sizeof(T)));
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p);
         p = nullptr;
         n = 0;
     }

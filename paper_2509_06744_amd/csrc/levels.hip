@@ -785,15 +785,16 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
         H->vec = opts->dtype == CHF_F64 ? CHF_F64 : CHF_F32;
         hipStream_t s = 0;
         const int nl = (int)H->lev.size();
-        for (int l = 0; l < nl - 1; ++l) {
+        // pattern and factor of level l on stream st
+        auto factor_level = [&](int l, hipStream_t st, int64_t* br) {
             chf_level_s& L = H->lev[l];
             if (L.preset) {
                 // caller-supplied pattern (e.g. a learned proposal)
             } else if (opts->pattern == 1) {
-                L.P = adaptive_pattern_impl(L.A, opts->tmax, opts->tau, s);
+                L.P = adaptive_pattern_impl(L.A, opts->tmax, opts->tau, st);
             } else {
                 chf_pattern P = nullptr;
-                int st = opts->pattern == 0 ? chf_pattern_lower(L.A, &P) : CHF_OK;
+                int rc = opts->pattern == 0 ? chf_pattern_lower(L.A, &P) : CHF_OK;
                 if (opts->pattern == 2) {
                     P = new chf_pattern_s;
                     P->nb = L.A->nb;
@@ -802,16 +803,16 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
                     for (int64_t k = 0; k <= P->nb; ++k) P->rowptr[k] = k;
                     for (int64_t k = 0; k < P->nb; ++k) P->colidx[k] = (int32_t)k;
                 }
-                if (st != CHF_OK) fail(st, chf_last_error());
+                if (rc != CHF_OK) fail(rc, chf_last_error());
                 L.P = P;
             }
             if (H->nest) {
                 // outer factor for A_l, inner factor for G0 A_l G0^T with
                 // Algorithm 1's pattern (same t_max and tau)
-                L.G0 = fsai_setup_impl(L.A, *L.P, opts->dtype, bad_row, s);
-                std::unique_ptr<chf_bsr_s> A1(bsr_triple_impl(L.A, *L.G0, s));
-                L.P1 = adaptive_pattern_impl(A1.get(), opts->tmax, opts->tau, s);
-                L.G1 = fsai_setup_impl(A1.get(), *L.P1, opts->dtype, bad_row, s);
+                L.G0 = fsai_setup_impl(L.A, *L.P, opts->dtype, br, st);
+                std::unique_ptr<chf_bsr_s> A1(bsr_triple_impl(L.A, *L.G0, st));
+                L.P1 = adaptive_pattern_impl(A1.get(), opts->tmax, opts->tau, st);
+                L.G1 = fsai_setup_impl(A1.get(), *L.P1, opts->dtype, br, st);
                 L.G = new chf_fsai_s;
                 L.G->nb = L.G0->nb;
                 L.G->b = L.G0->b;
@@ -819,13 +820,63 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
                 L.G->nest_outer = L.G0;
                 L.G->nest_inner = L.G1;
             } else {
-                L.G = fsai_setup_impl(L.A, *L.P, opts->dtype, bad_row, s);
+                L.G = fsai_setup_impl(L.A, *L.P, opts->dtype, br, st);
             }
-            if (v0 && v0[l]) {
-                lanczos_impl(L.A, *L.G, opts->dtype, opts->lanczos_iters, v0[l], opts->safety, &L.beta, nullptr, s);
-            }
+        };
+        auto bound_level = [&](int l, hipStream_t st) {
+            chf_level_s& L = H->lev[l];
+            if (v0 && v0[l])
+                lanczos_impl(L.A, *L.G, opts->dtype, opts->lanczos_iters, v0[l], opts->safety, &L.beta, nullptr, st);
+        };
+        // Level 0 is factored first. Its Lanczos bound (bandwidth-bound SpMVs)
+        // then runs on the caller's stream while a host thread sets up the
+        // coarser levels (latency-bound pattern and factor kernels) and the
+        // coarsest solve on a stream of its own; the levels share no data.
+        // Frees inside the overlapped part are deferred to its end (a free
+        // would synchronise the device and so wait for the other stream).
+        if (nl > 1) factor_level(0, s, bad_row);
+        hipStream_t s1 = nullptr;
+        std::thread worker;
+        std::exception_ptr werr, merr;
+        int64_t wbad = -1;
+        std::vector<void*> defer_main, defer_worker;
+        if (nl > 2) {
+            int dev = 0;
+            CHF_HIP(hipGetDevice(&dev));
+            CHF_HIP(hipStreamCreateWithFlags(&s1, hipStreamNonBlocking));
+            worker = std::thread([&, dev] {
+                set_free_deferral(&defer_worker);
+                try {
+                    CHF_HIP(hipSetDevice(dev));   // the current device is per host thread
+                    for (int l = 1; l < nl - 1; ++l) {
+                        factor_level(l, s1, &wbad);
+                        bound_level(l, s1);
+                    }
+                    build_coarse_dense(H->lev[nl - 1], s1);
+                    CHF_HIP(hipStreamSynchronize(s1));
+                } catch (...) {
+                    werr = std::current_exception();
+                }
+                set_free_deferral(nullptr);
+            });
+            set_free_deferral(&defer_main);
         }
-        build_coarse_dense(H->lev[nl - 1], s);
+        try {
+            if (nl > 1) bound_level(0, s);
+            if (nl <= 2) build_coarse_dense(H->lev[nl - 1], s);
+        } catch (...) {
+            merr = std::current_exception();
+        }
+        set_free_deferral(nullptr);
+        if (worker.joinable()) worker.join();
+        if (s1) (void)hipStreamDestroy(s1);
+        for (void* q : defer_main) dev_free(q);
+        for (void* q : defer_worker) dev_free(q);
+        if (merr) std::rethrow_exception(merr);
+        if (werr) {
+            if (bad_row && wbad >= 0) *bad_row = wbad;
+            std::rethrow_exception(werr);
+        }
         if (H->vec != CHF_F64)
             for (int l = 0; l < nl; ++l) (void)H->lev[l].A->sell(CHF_F32, s);
         alloc_vectors(*H);
