@@ -20,6 +20,18 @@
  *    contiguous; BSR column indices ascend within each row.
  *  - Vector element types follow the operator's working dtype: CHF_F64 ->
  *    double, CHF_F32 and CHF_BF16 (BF16 factor storage) -> float.
+ *
+ * Tuning overrides, read from the environment (results stay within the
+ * parity bounds of every setting; they exist for tests and measurement):
+ *  - CHF_FSAI_CONFIG="<width>,<tile threshold>": the local solver of
+ *    chf_fsai_setup (width 64, 128 or 256; rows wider than the threshold use
+ *    the tiled MFMA solver, 0 = never) instead of the autotuned choice.
+ *  - CHF_SPMV_SPLIT_BELOW=<slices>: SpMV layouts with fewer slices use one
+ *    workgroup per slice (default 2048; 0 = never).
+ *  - CHF_SPMV_NONTEMPORAL=0: plain instead of non-temporal matrix loads
+ *    (read once per process).
+ *  - CHF_ADAPTIVE_PLACEMENT=global|v|all: where Algorithm 1 keeps A[P,P]^{-1}
+ *    and V (global slot or LDS) instead of the automatic choice.
  */
 #ifndef CHF_H
 #define CHF_H
@@ -178,7 +190,10 @@ int chf_levels_add_coarse(chf_levels L, int64_t nc, const int64_t* p_rowptr,
  * v0[l], device double[N_l]); coarsest: dense FP64 Cholesky-based inverse.
  * v0 may be NULL only if every beta is set afterwards with
  * chf_levels_set_beta. On ENOTSPD *bad_row is set as in chf_fsai_setup
- * (the coarsest level reports -2). */
+ * (the coarsest level reports -2). Level 0 is set up on the null stream;
+ * the coarser levels are set up meanwhile by an internal host thread on a
+ * stream of its own, on the calling thread's current device. The call
+ * returns when all levels are done. */
 int chf_levels_setup(chf_levels L, const chf_level_opts* opts, const double* const* v0,
                      int64_t* bad_row);
 /* Use pattern P (copied; lower triangular with the diagonal) on level `level`
