@@ -130,14 +130,15 @@ __device__ void fsai_row(int64_t k, int b, const int* __restrict__ a_rowptr, con
 // ------------------------------------------------- tiled MFMA local solver --
 // For larger local systems (n > ntile, b <= 16) the factorisation works on
 // 16 x 16 tiles of the lower triangle, held in the workgroup's global scratch
-// slot (L2/MALL resident). Per tile column, one wavefront factors the diagonal
-// tile and inverts its factor in registers (the only sequential step); the
-// panel L_ik = A_ik L_kk^{-T} and the trailing update A_IJ -= L_Ik L_Jk^T are
-// FP64 MFMA products over the four wavefronts (v_mfma_f64_16x16x4: lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16] and receives
-// D[4 r + l / 16][l % 16] in register r). The b right-hand sides of
-// L^T Z = E are solved by tile rows, Z_I = L_II^{-T}(E_I - sum L_JI^T Z_J),
-// also on MFMA. Padding rows of the last tile are identity rows.
+// slot (L2/MALL resident), right-looking by pairs of tile columns. Per column,
+// one wavefront factors the diagonal tile and inverts its factor in registers
+// (the only sequential step); the panel L_ik = A_ik L_kk^{-T} and the
+// trailing update A_IJ -= L_Ik L_Jk^T + L_I,k+1 L_J,k+1^T are FP64 MFMA
+// products over the four wavefronts (v_mfma_f64_16x16x4: lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 r + l / 16][l % 16]
+// in register r). The b right-hand sides of L^T Z = E are solved by tile
+// rows, Z_I = L_II^{-T}(E_I - sum L_JI^T Z_J), also on MFMA. Padding rows of
+// the last tile are identity rows.
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ inline v4d mfma16(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
