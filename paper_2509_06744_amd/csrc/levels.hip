@@ -823,6 +823,15 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
                 L.G = fsai_setup_impl(L.A, *L.P, opts->dtype, br, st);
             }
         };
+        // the coarsest level's dense factorisation; a non-SPD operator reports -2
+        auto coarse_level = [&](hipStream_t st, int64_t* br) {
+            try {
+                build_coarse_dense(H->lev[nl - 1], st);
+            } catch (const Error& e) {
+                if (e.code == CHF_ENOTSPD && br) *br = -2;
+                throw;
+            }
+        };
         auto bound_level = [&](int l, hipStream_t st) {
             chf_level_s& L = H->lev[l];
             if (v0 && v0[l])
@@ -844,7 +853,7 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
             int dev = 0;
             CHF_HIP(hipGetDevice(&dev));
             CHF_HIP(hipStreamCreateWithFlags(&s1, hipStreamNonBlocking));
-            worker = std::thread([&, dev] {
+            auto work = [&, dev] {
                 set_free_deferral(&defer_worker);
                 try {
                     CHF_HIP(hipSetDevice(dev));   // the current device is per host thread
@@ -852,18 +861,24 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
                         factor_level(l, s1, &wbad);
                         bound_level(l, s1);
                     }
-                    build_coarse_dense(H->lev[nl - 1], s1);
+                    coarse_level(s1, &wbad);
                     CHF_HIP(hipStreamSynchronize(s1));
                 } catch (...) {
                     werr = std::current_exception();
                 }
                 set_free_deferral(nullptr);
-            });
+            };
+            try {
+                worker = std::thread(work);
+            } catch (...) {
+                (void)hipStreamDestroy(s1);
+                throw;
+            }
             set_free_deferral(&defer_main);
         }
         try {
             if (nl > 1) bound_level(0, s);
-            if (nl <= 2) build_coarse_dense(H->lev[nl - 1], s);
+            if (nl <= 2) coarse_level(s, bad_row);
         } catch (...) {
             merr = std::current_exception();
         }
@@ -874,7 +889,7 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
         for (void* q : defer_worker) dev_free(q);
         if (merr) std::rethrow_exception(merr);
         if (werr) {
-            if (bad_row && wbad >= 0) *bad_row = wbad;
+            if (bad_row && wbad != -1) *bad_row = wbad;
             std::rethrow_exception(werr);
         }
         if (H->vec != CHF_F64)

@@ -6,7 +6,7 @@ import pytest
 from oracle import multilevel, solver
 from oracle.bsr import from_problem
 from problems import make_problem, rhs
-from tests.helpers import dev, gpu_levels, host, oracle_levels, rel_err
+from tests.helpers import dev, gpu_levels, hierarchy_inputs, host, oracle_levels, rel_err, upload
 
 pytestmark = pytest.mark.gpu
 
@@ -104,3 +104,24 @@ def test_single_level_pcg_one_iteration(chf):
     x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
     it, hist, true_res, rc = chf.pcg_solve(L, dev(rhs(0, p.ndof)), x, rtol=1e-10, maxit=10)
     assert it == 1 and true_res < 1e-10
+
+
+# Zero weights for coarse block 0 in the last prolongator make the coarsest
+# Galerkin operator singular (its row 0 is zero), so its dense factorisation
+# fails: CHF_ENOTSPD with bad_row -2. With 2 levels the coarsest level is
+# factored on the calling thread, with 3 on the set-up's worker thread.
+@pytest.mark.parametrize("levels", [2, 3])
+def test_error_coarsest_not_spd_reports_minus_two(chf, levels):
+    from problems import level_basis
+    p = make_problem(16, 2, 3, 2, seed=0)
+    A = upload(p)
+    pro, starts = hierarchy_inputs(p.n, p.dim, p.b, levels, 0)
+    L = chf.levels_create(A)
+    for i, (ps, basis) in enumerate(zip(pro, level_basis(p, levels))):
+        ps = ps.tocsr().copy()
+        if i == levels - 2:
+            ps.data[ps.indices == 0] = 0.0
+        chf.levels_add_coarse(L, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
+    with pytest.raises(chf.ChfError) as ei:
+        chf.levels_setup(L, degree=2, pattern=0, v0=[dev(s) for s in starts[:-1]])
+    assert ei.value.code == -3 and ei.value.bad_row == -2
