@@ -264,7 +264,7 @@ __device__ inline TV sell_lane_sum(int b, int S, int L, int lane, int lr, int j_
         const int64_t stride = (int64_t)NQ * L * V;
         const TA* v = vals + (int64_t)j_first * stride + lane * V;
         const int* cp = cols + (int64_t)j_first * S + lr;
-#pragma unroll 2
+#pragma unroll 1
         for (int j = j_first; j < j1; j += STEP) {
             const TV* xc = x + (int64_t)(*cp) * BT;
 #pragma unroll
