@@ -565,13 +565,11 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s, DevBuf<
     int64_t stride = (int64_t)FSAI_MAXN * (FSAI_MAXN + 1) / 2 + (int64_t)FSAI_MAXN * a.b;
     if (tiled)
         stride = std::max<int64_t>(stride, (int64_t)tmaxtiles * (tmaxtiles + 1) / 2 * 256 + (int64_t)tmaxtiles * 256);
-    // global scratch only when some row exceeds the LDS limit or is tiled
-    scratch.alloc(1);
+    // global scratch only when some row exceeds the LDS limit or is tiled;
+    // the buffer only grows, so repeated launches (the autotuner) reuse it
+    const size_t need = (a.nmax > nlds || tiled) ? (size_t)grid * stride : 1;
+    if (scratch.n < need) scratch.alloc(need);
     double* scr = scratch.p;
-    if (a.nmax > nlds || tiled) {
-        scratch.alloc((size_t)grid * stride);
-        scr = scratch.p;
-    }
     fill_zero(a.counter, sizeof(int), s);
     if (shm > 64 * 1024) {
         CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
@@ -613,26 +611,42 @@ static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order
     }
     TuneVal best = nmax > 64 ? TuneVal{128, NO_TILES} : TuneVal{64, NO_TILES};
     if (a.nrows >= 4096) {
-        // an evenly strided sample of the size-sorted order keeps the size mix
-        const int64_t ns = 8192;
-        std::vector<int64_t> smp_order(std::min<int64_t>(ns, a.nrows));
-        for (size_t i = 0; i < smp_order.size(); ++i)
-            smp_order[i] = order_host[(int64_t)i * a.nrows / (int64_t)smp_order.size()];
-        DevBuf<int64_t> d_smp(smp_order.size());
-        d_smp.upload(smp_order.data(), smp_order.size(), s);
-        SetupArgs smp = a;
-        smp.nrows = (int64_t)smp_order.size();
-        smp.order = d_smp.p;
-        double best_t = 1e30;
+        // evenly strided samples of the size-sorted order keep the size mix
+        auto sample = [&](int64_t ns) {
+            std::vector<int64_t> o(std::min<int64_t>(ns, a.nrows));
+            for (size_t i = 0; i < o.size(); ++i) o[i] = order_host[(int64_t)i * a.nrows / (int64_t)o.size()];
+            return o;
+        };
         DevBuf<double> scratch;
-        for (const TuneVal& c : cands) {
-            launch_setup(c, smp, s, scratch);  // warm-up
+        // seconds of one launch on `rows` (device order), after a warm-up launch
+        auto time_on = [&](const TuneVal& c, const DevBuf<int64_t>& rows, int64_t n) {
+            SetupArgs smp = a;
+            smp.nrows = n;
+            smp.order = rows.p;
+            launch_setup(c, smp, s, scratch);
             CHF_HIP(hipStreamSynchronize(s));
             auto t0 = std::chrono::steady_clock::now();
             launch_setup(c, smp, s, scratch);
             CHF_HIP(hipStreamSynchronize(s));
-            double dt = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-            if (dt < best_t) { best_t = dt; best = c; }
+            return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        };
+        // screening on 1,024 rows drops candidates more than twice as slow as
+        // the best one (the scalar solvers on wide rows are tens of times slower)
+        const std::vector<int64_t> small = sample(1024), full = sample(8192);
+        DevBuf<int64_t> d_small(small.size()), d_full(full.size());
+        d_small.upload(small.data(), small.size(), s);
+        d_full.upload(full.data(), full.size(), s);
+        std::vector<double> ts(cands.size());
+        double ts_best = 1e30;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            ts[i] = time_on(cands[i], d_small, (int64_t)small.size());
+            ts_best = std::min(ts_best, ts[i]);
+        }
+        double best_t = 1e30;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            if (ts[i] > 2.0 * ts_best) continue;
+            const double dt = time_on(cands[i], d_full, (int64_t)full.size());
+            if (dt < best_t) { best_t = dt; best = cands[i]; }
         }
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
