@@ -170,10 +170,12 @@ __global__ void k_basis_t(int64_t nb, int b, const TV* __restrict__ T, const TV*
 // x_i += T_i z_i with z_i = sum_{(I, w) in P(i)} w x_c[I]. A wavefront holds
 // S = 64 / b block rows, lane = local_row * b + r: the lane forms component r
 // of z_i once, and the row's b lanes exchange their components by shuffles.
-template <typename TV>
-__global__ void k_prolong_add_basis(int64_t nf, int b, const int64_t* __restrict__ p_rowptr,
+// BT > 0 fixes b at compile time, so the lane's row of T_i is loaded at once.
+template <int BT, typename TV>
+__global__ void k_prolong_add_basis(int64_t nf, int brt, const int64_t* __restrict__ p_rowptr,
                                     const int* __restrict__ p_col, const double* __restrict__ p_val,
                                     const TV* __restrict__ T, const TV* __restrict__ xc, TV* __restrict__ x) {
+    const int b = BT ? BT : brt;
     const int S = 64 / b;
     const int lane = threadIdx.x & 63;
     const int64_t wv = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
@@ -183,11 +185,19 @@ __global__ void k_prolong_add_basis(int64_t nf, int b, const int64_t* __restrict
     TV z = 0;
     if (active)
         for (int64_t e = p_rowptr[i]; e < p_rowptr[i + 1]; ++e) z += (TV)p_val[e] * xc[(int64_t)p_col[e] * b + r];
-    const TV* Ti = T + i * b * b + r * b;
+    const TV* Ti = T + (active ? i : 0) * b * b + r * b;
     TV acc = 0;
-    for (int c = 0; c < b; ++c) {
-        const TV zc = __shfl(z, lr * b + c, 64);   // lanes past S * b read a wrapped lane, unused
-        if (active) acc += Ti[c] * zc;
+    if constexpr (BT > 0) {
+        TV t[BT];
+#pragma unroll
+        for (int c = 0; c < BT; ++c) t[c] = active ? Ti[c] : (TV)0;
+#pragma unroll
+        for (int c = 0; c < BT; ++c) acc += t[c] * __shfl(z, lr * BT + c, 64);   // lanes past S * b: unused
+    } else {
+        for (int c = 0; c < b; ++c) {
+            const TV zc = __shfl(z, lr * b + c, 64);   // lanes past S * b read a wrapped lane, unused
+            if (active) acc += Ti[c] * zc;
+        }
     }
     if (active) x[i * b + r] += acc;
 }
@@ -552,12 +562,21 @@ static void prolong_add(chf_levels_s& H, int l, const void* xc, void* x, hipStre
     if (L.has_T) {
         const int64_t waves = (nf + 64 / b - 1) / (64 / b);
         dim3 gw((unsigned)((waves + 3) / 4));   // four wavefronts per 256-wide workgroup
-        if (H.vec == CHF_F64)
-            hipLaunchKernelGGL((k_prolong_add_basis<double>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
-                               L.d_p_col.p, L.d_p_val.p, (const double*)L.d_T64.p, (const double*)xc, (double*)x);
-        else
-            hipLaunchKernelGGL((k_prolong_add_basis<float>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
-                               L.d_p_col.p, L.d_p_val.p, (const float*)L.d_T32.p, (const float*)xc, (float*)x);
+        if (H.vec == CHF_F64) {
+            if (b == 10)
+                hipLaunchKernelGGL((k_prolong_add_basis<10, double>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
+                                   L.d_p_col.p, L.d_p_val.p, (const double*)L.d_T64.p, (const double*)xc, (double*)x);
+            else
+                hipLaunchKernelGGL((k_prolong_add_basis<0, double>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
+                                   L.d_p_col.p, L.d_p_val.p, (const double*)L.d_T64.p, (const double*)xc, (double*)x);
+        } else {
+            if (b == 10)
+                hipLaunchKernelGGL((k_prolong_add_basis<10, float>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
+                                   L.d_p_col.p, L.d_p_val.p, (const float*)L.d_T32.p, (const float*)xc, (float*)x);
+            else
+                hipLaunchKernelGGL((k_prolong_add_basis<0, float>), gw, dim3(256), 0, s, nf, b, L.d_p_rowptr.p,
+                                   L.d_p_col.p, L.d_p_val.p, (const float*)L.d_T32.p, (const float*)xc, (float*)x);
+        }
         CHF_LAUNCH_CHECK();
         return;
     }
