@@ -412,10 +412,16 @@ def main():
     torch.cuda.synchronize()
     t_fsai = time.perf_counter() - t
     del Gtmp
-    setup64.update({"adaptive_pattern_level0_ms": 1e3 * t_pat, "fsai_setup_level0_ms": 1e3 * t_fsai})
-    log(f"set-up done: {setup64}")
     _, G0, _ = chf.levels_get(H, 0)
     beta0 = chf.levels_get_beta(H, 0)
+    # the level-0 spectral bound alone (100 Lanczos steps on G A G^T), timed
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    chf.lmax_lanczos(A, G0, v0[0])
+    t_lz = time.perf_counter() - t
+    setup64.update({"adaptive_pattern_level0_ms": 1e3 * t_pat, "fsai_setup_level0_ms": 1e3 * t_fsai,
+                     "lanczos_level0_ms": 1e3 * t_lz})
+    log(f"set-up done: {setup64}")
     N = A.info()[0] * b
 
     # ---- timed region: K smoother applications on level 0 (x != 0)
