@@ -521,6 +521,28 @@ def main():
                          "flexible_cg": flex}
             if setup:
                 res[name]["setup"] = {kk: round(v, 2) for kk, v in setup.items()}
+            if dt != chf.F64:
+                # one level-0 smoother application with this hierarchy's operators
+                # (A in FP32; G in FP32 or BF16; FP32 vectors), timed like the FP64 one
+                A0m, G0m, _ = chf.levels_get(Hh, 0)
+                beta_m = chf.levels_get_beta(Hh, 0)
+                b32 = bd.float()
+                x32 = torch.zeros(N, dtype=torch.float32, device=dev)
+                w32 = torch.zeros(3 * N, dtype=torch.float32, device=dev)
+                for _ in range(args.warmup):
+                    chf.cheb4_smooth(A0m, G0m, beta_m, k, b32, x32, work=w32, dtype=dt)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for _ in range(args.steps):
+                    chf.cheb4_smooth(A0m, G0m, beta_m, k, b32, x32, work=w32, dtype=dt)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms_m = e0.elapsed_time(e1) / args.steps
+                sg = 4 if dt == chf.F32 else 2
+                b_m = k * (nnzb * (b * b * 4 + 4) + 2 * nnzg * (b * b * sg + 4) + 10 * N * 4)
+                res[name]["smoother"] = {"ms_per_application": round(ms_m, 5), "algorithmic_bytes_per_application": b_m,
+                                         "achieved_GBs": round(b_m / (ms_m * 1e-3) / 1e9, 1),
+                                         "hbm_frac": round(b_m / (ms_m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             log(f"PCG {name}: {res[name]}")
             if Hh is not H:
                 Hh.destroy()
