@@ -62,7 +62,17 @@ __global__ void k_sell_pack(int64_t total, int b, int S, int L, int V, const int
         int64_t slot = e / bl;
         int rem = (int)(e - slot * bl);
         int lane, c;
-        if (V == 4) {
+        if (V == 8) {
+            // b = 10, BF16: runs of 8 and 2 columns (L * 8, L * 2 values)
+            if (rem < 8 * L) {
+                lane = rem / 8;
+                c = rem - lane * 8;
+            } else {
+                const int rem2 = rem - 8 * L;
+                lane = rem2 / 2;
+                c = 8 + (rem2 - lane * 2);
+            }
+        } else if (V == 4) {
             // b = 10: runs of 4, 4 and 2 columns (L * 4, L * 4, L * 2 values)
             if (rem < 8 * L) {
                 const int q = rem / (4 * L), rem2 = rem - q * 4 * L;
@@ -91,10 +101,12 @@ __global__ void k_sell_pack(int64_t total, int b, int S, int L, int V, const int
 }
 
 // Lane vector width of the layout for the block sizes with a specialised
-// SpMV: b = 10 stores pairs of columns for FP64 (16-byte loads) and runs of
-// 4, 4 and 2 columns for 4- and 2-byte storage (16- and 8-byte loads for
-// FP32), marked V = 4.
-static int sell_vec_width(int b, chf_dtype t) { return b == 10 ? (t == CHF_F64 ? 2 : 4) : 1; }
+// SpMV: b = 10 stores pairs of columns for FP64 (16-byte loads), runs of 4, 4
+// and 2 columns for FP32 (16- and 8-byte loads, marked V = 4) and runs of 8
+// and 2 columns for BF16 (16- and 4-byte loads, marked V = 8).
+static int sell_vec_width(int b, chf_dtype t) {
+    return b == 10 ? (t == CHF_F64 ? 2 : t == CHF_F32 ? 4 : 8) : 1;
+}
 
 void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, bool transpose,
                 chf_dtype dtype, hipStream_t s) {
@@ -232,6 +244,22 @@ struct Pair<4, bf16_t, TV, NTL> {
     }
 };
 
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+template <typename TV, bool NTL>
+struct Pair<8, bf16_t, TV, NTL> {
+    __device__ static inline TV dot(const bf16_t* v, const TV* x) {
+        u4v u;
+        if constexpr (NTL)
+            u = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(v));
+        else
+            u = *reinterpret_cast<const u4v*>(v);
+        auto lo = [](unsigned w) { return (TV)bf16_bits_to_f32((uint16_t)(w & 0xffffu)); };
+        auto hi = [](unsigned w) { return (TV)bf16_bits_to_f32((uint16_t)(w >> 16)); };
+        return ((lo(u.x) * x[0] + hi(u.x) * x[1]) + (lo(u.y) * x[2] + hi(u.y) * x[3])) +
+               ((lo(u.z) * x[4] + hi(u.z) * x[5]) + (lo(u.w) * x[6] + hi(u.w) * x[7]));
+    }
+};
+
 __device__ inline int64_t xcd_slice_block(int64_t nwork_blocks) {
     // gridDim.x is a multiple of 8; block id b runs on XCD b % 8
     const int64_t per = gridDim.x / 8;
@@ -245,7 +273,20 @@ __device__ inline TV sell_lane_sum(int b, int S, int L, int lane, int lr, int j_
                                    const int* __restrict__ cols, const TA* __restrict__ vals,
                                    const TV* __restrict__ x) {
     TV acc = 0;
-    if constexpr (BT == 10 && V == 4) {
+    if constexpr (BT == 10 && V == 8) {
+        // runs of 8 and 2 columns per slot (BF16: 16- and 4-byte loads)
+        const int64_t stride = (int64_t)10 * L;
+        const TA* v = vals + (int64_t)j_first * stride;
+        const int* cp = cols + (int64_t)j_first * S + lr;
+#pragma unroll 2
+        for (int j = j_first; j < j1; j += STEP) {
+            const TV* xc = x + (int64_t)(*cp) * 10;
+            acc += Pair<8, TA, TV, NTL>::dot(v + lane * 8, xc);
+            acc += Pair<2, TA, TV, NTL>::dot(v + 8 * L + lane * 2, xc + 8);
+            v += STEP * stride;
+            cp += STEP * S;
+        }
+    } else if constexpr (BT == 10 && V == 4) {
         // runs of 4, 4 and 2 columns per slot (16-, 16- and 8-byte loads)
         const int64_t stride = (int64_t)10 * L;
         const TA* v = vals + (int64_t)j_first * stride;
@@ -418,8 +459,10 @@ static void launch_spmv_b(const Sell& A, const void* x, void* y, const void* bv,
         case 10:
             if constexpr (sizeof(TA) == 8)
                 launch_spmv_t<10, 2, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
-            else
+            else if constexpr (sizeof(TA) == 4)
                 launch_spmv_t<10, 4, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
+            else
+                launch_spmv_t<10, 8, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
             break;
         case 21: launch_spmv_t<21, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
         default: launch_spmv_t<0, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
