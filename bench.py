@@ -160,7 +160,7 @@ def setup3d_leg(args, chf, torch):
 
 
 def comparators_leg(args, chf, torch, dev, H, A, bd, N, k):
-    """The smoothers and cycles that Sec. 3.2 and Sec. 5 compare, on the same
+    """The smoothers and cycles that Sec. 3.1 and Sec. 5 compare, on the same
     FP64 hierarchy (same patterns, factors and bounds beta_l): fourth-kind
     Chebyshev, first-kind Chebyshev on [0.3 beta, beta], Richardson
     (omega = 1, S = (I - MA)^k), each in V(k,k), and fourth-kind Chebyshev in

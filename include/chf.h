@@ -152,13 +152,13 @@ int chf_lmax_lanczos(chf_bsr A, chf_fsai G, chf_dtype dtype, int iters, const do
 int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree,
                      const void* b, void* x, int x_is_zero, void* work, hipStream_t stream);
 
-/* Comparators of Sec. 3.2, with the same arguments, layout and work buffer
+/* Comparators of Sec. 3.1, with the same arguments, layout and work buffer
  * as chf_cheb4_smooth:
  * - chf_cheb1_smooth: Algorithm 2 (Chebyshev iteration of the first kind)
  *   with the preconditioner M, on the smoothing interval [alpha, beta]
- *   (0 < alpha < beta; Sec. 3.2 takes alpha = rho lambda_max, rho in (0,1)).
+ *   (0 < alpha < beta; Sec. 3.1 takes alpha = rho lambda_max, rho in (0,1)).
  * - chf_richardson_smooth: Richardson smoothing x <- x + omega M (b - A x),
- *   `degree` times, i.e. S = (I - omega M A)^degree (omega = 1 in Sec. 3.2).
+ *   `degree` times, i.e. S = (I - omega M A)^degree (omega = 1 in Sec. 3.1).
  * EINVAL for degree < 1 or parameters outside these ranges. */
 int chf_cheb1_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double alpha, double beta, int degree,
                      const void* b, void* x, int x_is_zero, void* work, hipStream_t stream);

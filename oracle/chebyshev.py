@@ -1,8 +1,9 @@
 """Polynomial smoothers of Sec. 3: fourth-kind Chebyshev (Algorithm 3), and
-the comparators of Sec. 3.2, first-kind Chebyshev (Algorithm 2) and
+the comparators of Sec. 3.1, first-kind Chebyshev (Algorithm 2) and
 Richardson smoothing S = (I - omega M A)^k.
 
-``cheb4``, ``cheb1`` and ``richardson`` follow their algorithms step by step.
+``cheb4``, ``cheb1`` and ``richardson`` derive each algorithm's per-step
+coefficients first and then run one shared increment loop.
 ``w4`` and ``w4_hat`` evaluate the polynomials of Eq. chebyshev_4th_kind
 through the three-term recurrence that follows it; ``t1_hat`` evaluates
 Eq. chebyshev_1st_kind with NumPy's Chebyshev series. They serve the pins in
@@ -14,26 +15,56 @@ from __future__ import annotations
 import numpy as np
 
 
+def _polynomial_smoother(apply_a, apply_m, b, x0, carry, scale, x_is_zero: bool):
+    """Shared driver of the polynomial smoothers of Sec. 3.
+
+    Every smoother here moves x by an increment that mixes the previous
+    increment with the preconditioned residual of the current iterate:
+        z_i = M (b - A x_{i-1}),
+        delta_i = carry[i] delta_{i-1} + scale[i] z_i   (carry[0] unused),
+        x_i = x_{i-1} + delta_i,
+    for i = 0 .. len(scale) - 1. The coefficients carry the method; the loop
+    is the same for all of them. Vectors keep the dtype of b (x0 is cast to
+    it), so the same code evaluates the smoother in FP64 or in FP32.
+    """
+    if x_is_zero:
+        x = np.zeros_like(b)
+    else:
+        x = np.array(x0, dtype=b.dtype, copy=True)
+    delta = None
+    for i, (cf, sf) in enumerate(zip(carry, scale)):
+        res = b.copy() if (x_is_zero and i == 0) else b - apply_a(x)
+        z = apply_m(res)
+        delta = sf * z if delta is None else cf * delta + sf * z
+        x = x + delta
+    return x
+
+
+def cheb4_coefficients(beta: float, k: int):
+    """Increment coefficients of Algorithm 3 for degree k >= 1.
+
+    Algorithm 3 moves x by (4 / beta) mu_i p_i with mu_i = (2i-1)/(2i+1)
+    (mu_1 = 1/3 and mu_{i+1} = 1 / (2 - mu_i)) and p_i = mu_{i-1}^2 p_{i-1}
+    + M r_{i-1}. For the increment delta_i = (4 / beta) mu_i p_i this gives
+    delta_i = mu_i mu_{i-1} delta_{i-1} + (4 / beta) mu_i M r_{i-1}, where
+    mu_i mu_{i-1} = (2i-3)/(2i+1).
+    """
+    if k < 1:
+        raise ValueError("degree must be >= 1")
+    mu = [(2 * i - 1) / (2 * i + 1) for i in range(1, k + 1)]
+    scale = [4.0 * m / beta for m in mu]
+    carry = [0.0] + [mu[i] * mu[i - 1] for i in range(1, k)]
+    return carry, scale
+
+
 def cheb4(apply_a, apply_m, b, x0, beta: float, k: int, x_is_zero: bool = False):
     """Algorithm 3: Chebyshev iteration of the fourth kind, degree k >= 1.
 
     apply_a(v) = A v, apply_m(v) = M v, beta >= lambda_max(MA).
     x_is_zero: x0 is zero, so the first residual is b itself.
     """
-    if k < 1:
-        raise ValueError("degree must be >= 1")
-    x = np.zeros_like(b) if x_is_zero else np.array(x0, dtype=np.float64, copy=True)
-    r = b.copy() if x_is_zero else b - apply_a(x)
-    p = apply_m(r)
-    mu = 1.0 / 3.0
-    d = 4.0 / beta
-    x = x + d * mu * p
-    for _ in range(2, k + 1):
-        r = b - apply_a(x)
-        p = mu * mu * p + apply_m(r)
-        mu = 1.0 / (2.0 - mu)
-        x = x + d * mu * p
-    return x
+    carry, scale = cheb4_coefficients(beta, k)
+    return _polynomial_smoother(apply_a, apply_m, b, x0, carry, scale, x_is_zero)
 
 
 def w4(k: int, t):
@@ -91,43 +122,47 @@ def cheb4_spectral(gmat: np.ndarray, amat: np.ndarray, b, x0, beta: float, k: in
     return x0 + gmat.T @ (v @ (q * (v.T @ (gmat @ r0))))
 
 
-def cheb1(apply_a, apply_m, b, x0, alpha: float, beta: float, k: int, x_is_zero: bool = False):
-    """Algorithm 2 (Chebyshev iteration of the first kind, degree k >= 1) with
-    the preconditioner M applied to every residual, on [alpha, beta].
+def cheb1_coefficients(alpha: float, beta: float, k: int):
+    """Increment coefficients of Algorithm 2 on [alpha, beta], degree k >= 1.
 
-    As a smoother (Sec. 3.2) [alpha, beta] covers only the upper part of the
-    spectrum of MA: alpha = rho lambda_max, rho in (0, 1)."""
+    With c = (alpha + beta)/2 and d = (beta - alpha)/2, Algorithm 2 moves x by
+    omega_i p_i, where omega_1 = 1/c, psi_1 = (d omega_1)^2 / 2,
+    omega_{i+1} = 1 / (c - psi_i / omega_i), psi_{i+1} = (d omega_{i+1} / 2)^2
+    and p_{i+1} = M r_i + psi_i p_i. The increment delta_i = omega_i p_i
+    therefore obeys delta_{i+1} = (omega_{i+1} psi_i / omega_i) delta_i +
+    omega_{i+1} M r_i.
+    """
     if k < 1:
         raise ValueError("degree must be >= 1")
     if not 0 < alpha < beta:
         raise ValueError("need 0 < alpha < beta")
     c = 0.5 * (alpha + beta)
     d = 0.5 * (beta - alpha)
-    x = np.zeros_like(b) if x_is_zero else np.array(x0, dtype=np.float64, copy=True)
-    r = b.copy() if x_is_zero else b - apply_a(x)
-    p = apply_m(r)
-    omega = 1.0 / c
-    psi = 0.5 * (d * omega) ** 2
-    x = x + omega * p
-    for _ in range(2, k + 1):
-        r = b - apply_a(x)
-        p = apply_m(r) + psi * p
-        omega = 1.0 / (c - psi / omega)
-        psi = (d * omega / 2.0) ** 2
-        x = x + omega * p
-    return x
+    omega = [1.0 / c]
+    psi = [0.5 * (d * omega[0]) ** 2]
+    for _ in range(1, k):
+        omega.append(1.0 / (c - psi[-1] / omega[-1]))
+        psi.append((d * omega[-1] / 2.0) ** 2)
+    carry = [0.0] + [omega[i] * psi[i - 1] / omega[i - 1] for i in range(1, k)]
+    return carry, omega
+
+
+def cheb1(apply_a, apply_m, b, x0, alpha: float, beta: float, k: int, x_is_zero: bool = False):
+    """Algorithm 2 (Chebyshev iteration of the first kind, degree k >= 1) with
+    the preconditioner M applied to every residual, on [alpha, beta].
+
+    As a smoother (Sec. 3.1) [alpha, beta] covers only the upper part of the
+    spectrum of MA: alpha = rho lambda_max, rho in (0, 1)."""
+    carry, scale = cheb1_coefficients(alpha, beta, k)
+    return _polynomial_smoother(apply_a, apply_m, b, x0, carry, scale, x_is_zero)
 
 
 def richardson(apply_a, apply_m, b, x0, omega: float, k: int, x_is_zero: bool = False):
     """Richardson smoothing: k steps x <- x + omega M (b - A x), i.e.
-    S = (I - omega M A)^k (Sec. 3.2 takes omega = 1)."""
+    S = (I - omega M A)^k (Sec. 3.1 takes omega = 1)."""
     if k < 1:
         raise ValueError("degree must be >= 1")
-    x = np.zeros_like(b) if x_is_zero else np.array(x0, dtype=np.float64, copy=True)
-    for i in range(k):
-        r = b.copy() if (x_is_zero and i == 0) else b - apply_a(x)
-        x = x + omega * apply_m(r)
-    return x
+    return _polynomial_smoother(apply_a, apply_m, b, x0, [0.0] * k, [omega] * k, x_is_zero)
 
 
 def t1_hat(k: int, lam, alpha: float, beta: float):

@@ -385,6 +385,9 @@ __global__ __launch_bounds__(256) void k_dense_gemv(int64_t n, int64_t ld, const
 __global__ void k_pcg_xr(int64_t n, const double* __restrict__ scal, const double* __restrict__ p,
                          const double* __restrict__ q, double* __restrict__ x, double* __restrict__ r,
                          double* __restrict__ rold) {
+    // breakdown (p^T A p <= 0 or r^T z <= 0, NaN included): leave x and r at
+    // the last good iterate; the host reads the same scalars and stops
+    if (!(scal[1] > 0.0) || !(scal[0] > 0.0)) return;
     const double alpha = scal[0] / scal[1];
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] += alpha * p[i];
@@ -1076,6 +1079,7 @@ extern "C" int chf_pcg_solve(chf_levels H, const double* b, double* x, double rt
             CHF_HIP(hipMemcpyAsync(hs, sc, 24, hipMemcpyDeviceToHost, s));
             CHF_HIP(hipStreamSynchronize(s));
             if (!(hs[1] > 0)) { status = CHF_EBREAKDOWN; set_error("PCG breakdown: p^T A p <= 0"); break; }
+            if (!(hs[0] > 0)) { status = CHF_EBREAKDOWN; set_error("PCG breakdown: r^T z <= 0"); break; }
             const double rel = std::sqrt(hs[2]) / bnorm;
             if (relres_hist) relres_hist[it] = rel;
             if (!std::isfinite(rel)) { status = CHF_EBREAKDOWN; set_error("PCG produced a non-finite residual"); break; }

@@ -3,8 +3,8 @@
 // with per-step scalars formed on the host, so nothing is read back:
 //   - Algorithm 3 (Chebyshev iteration of the fourth kind) on [0, beta];
 //   - Algorithm 2 (Chebyshev iteration of the first kind), preconditioned,
-//     on a smoothing interval [alpha, beta] (Sec. 3.2);
-//   - Richardson smoothing S = (I - omega M A)^k (Sec. 3.2, omega = 1 there).
+//     on a smoothing interval [alpha, beta] (Sec. 3.1);
+//   - Richardson smoothing S = (I - omega M A)^k (Sec. 3.1, omega = 1 there).
 //
 // Each step is three kernels: r = b - A x (skipped in the first step when x
 // starts at zero), t = G r, and z = G^T t fused with the update of p and x.

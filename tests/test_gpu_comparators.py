@@ -1,4 +1,4 @@
-"""GPU parity of the comparator smoothers of Sec. 3.2 (first-kind Chebyshev,
+"""GPU parity of the comparator smoothers of Sec. 3.1 (first-kind Chebyshev,
 Algorithm 2; Richardson smoothing), of the V(2k,0) cycle of Sec. 5 and of
 BiCGStab, its outer solver, against the oracle, through the C ABI; error
 paths of the new entry points."""

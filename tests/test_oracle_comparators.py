@@ -1,4 +1,4 @@
-"""Pins for the oracle's comparator smoothers of Sec. 3.2 and the V(2k,0)
+"""Pins for the oracle's comparator smoothers of Sec. 3.1 and the V(2k,0)
 cycle of Sec. 5:
 
 - Algorithm 2 (first-kind Chebyshev) against Eq. chebyshev_1st_kind evaluated

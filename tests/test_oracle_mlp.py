@@ -60,3 +60,28 @@ def test_topk_ties_to_smaller_column():
     assert list(pcol[prow[2]:prow[3]]) == [0, 2]
     assert list(pcol[prow[1]:prow[2]]) == [0, 1]
     assert list(pcol[prow[0]:prow[1]]) == [0]
+
+
+def test_a2_candidates_match_scipy_structure():
+    # candidates = strictly lower part of the block pattern of A^2, formed here
+    # by SciPy's sparse product of the 0/1 block structure (no cancellation)
+    import scipy.sparse as sp
+    for n, dim, b in [(7, 2, 2), (4, 3, 1)]:
+        p = make_problem(n, dim, b, 2, seed=1)
+        a = from_problem(p)
+        s = sp.csr_matrix((np.ones(p.nnzb), p.colidx, p.rowptr), shape=(p.nb, p.nb))
+        s2 = sp.tril(s @ s, k=-1, format="csr")
+        s2.sort_indices()
+        crow, ccol = mlp.a2_candidates(a)
+        assert np.array_equal(crow, s2.indptr.astype(np.int64))
+        assert np.array_equal(ccol, s2.indices.astype(np.int64))
+
+
+def test_labels_hand_built():
+    # rows 0..2; row 1 has candidates {0}, row 2 has {0, 1};
+    # pattern P_1 = {1}, P_2 = {0, 2}
+    crow = np.array([0, 0, 1, 3])
+    ccol = np.array([0, 0, 1])
+    prow = np.array([0, 1, 2, 4])
+    pcol = np.array([0, 1, 0, 2])
+    assert list(mlp.labels(crow, ccol, prow, pcol)) == [0.0, 1.0, 0.0]

@@ -111,6 +111,32 @@ def test_energy_factor_converges():
     assert 0 < rho < 0.9
 
 
+@pytest.mark.parametrize("ncyc", [1, 4, 9])
+def test_energy_factor_against_dense_error_operator(ncyc):
+    # Two levels with an exact coarse solve: the cycle on b = 0 maps e to
+    # E e, E = p(MA) (I - P A_c^{-1} P^T A) p(MA), p = W^_k on [0, beta], with
+    # p(MA) formed from the eigendecomposition of G A G^T. The factor after n
+    # cycles is (||E^n e0||_A / ||e0||_A)^{1/n}.
+    from oracle import chebyshev
+    from problems import uniform_start
+    p, levels = _hier(n=8, b=3, levels=2)
+    k = 3
+    lev = levels[0]
+    ad, gd, pb = lev.a.dense(), lev.g.dense(), lev.pb.toarray()
+    bmat = gd @ ad @ gd.T
+    lam, v = np.linalg.eigh(0.5 * (bmat + bmat.T))
+    q = (1.0 - chebyshev.w4_hat(k, lam, lev.beta)) / lam
+    smooth = np.eye(ad.shape[0]) - gd.T @ (v * q) @ v.T @ gd @ ad
+    coarse = np.eye(ad.shape[0]) - pb @ np.linalg.solve(pb.T @ ad @ pb, pb.T @ ad)
+    err = smooth @ coarse @ smooth
+    e0 = uniform_start(3, p.ndof)
+    en = np.linalg.matrix_power(err, ncyc) @ e0
+    want = np.sqrt((en @ ad @ en) / (e0 @ ad @ e0)) ** (1.0 / ncyc)
+    rho, n = multilevel.energy_factor(levels, e0, k, tol=0.0, maxit=ncyc)
+    assert n == ncyc
+    assert abs(rho - want) < 1e-10 * want
+
+
 def test_pcg_flexible_variant_close():
     p, levels = _hier(n=16, b=3, levels=3)
     b = rhs(1, p.ndof)
