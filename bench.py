@@ -168,7 +168,6 @@ def comparators_leg(args, chf, torch, dev, H, A, bd, N, k):
     U(-1,1) error, and a Krylov solve to 1e-8: CG for the symmetric cycles,
     flexible CG and BiCGStab (two cycles per iteration) for V(2k,0), and
     BiCGStab with V(k,k) for reference."""
-    from paper_2509_06744_amd import learned
     from problems import uniform_start
     e0 = torch.from_numpy(uniform_start(0, N)).to(dev)
     runs = [("cheb4_Vkk", chf.SMOOTH_CHEB4, 0.0, chf.CYCLE_VKK),
@@ -183,7 +182,7 @@ def comparators_leg(args, chf, torch, dev, H, A, bd, N, k):
         rec = {}
         bicg = name.endswith("_bicgstab")
         if not bicg:
-            rho, ncyc = learned.energy_factor(H, A, e0, maxit=30)
+            rho, ncyc = chf.levels_energy_factor(H, e0, maxit=30)
             rec["rho_A"], rec["cycles"] = round(rho, 5), ncyc
         flex = cyc == chf.CYCLE_V2K0
         xs = torch.zeros(N, dtype=torch.float64, device=dev)
@@ -215,14 +214,13 @@ def nested_leg(args, chf, torch, dev, A, bd, N, k, pro, bases, v0, H_plain, plai
     hierarchy: set-up time, energy-norm cycle factor, PCG to 1e-8 and the time
     of one level-0 smoother application (five kernels per step instead of
     three). Sec. 5 observes that nested t_max = c behaves like plain 2c."""
-    from paper_2509_06744_amd import learned
     from problems import uniform_start
     e0 = torch.from_numpy(uniform_start(0, N)).to(dev)
     out = {}
 
     def measure(H, name, setup_ms):
         rec = {"levels_setup_ms": round(setup_ms, 1)}
-        rho, ncyc = learned.energy_factor(H, A, e0, maxit=30)
+        rho, ncyc = chf.levels_energy_factor(H, e0, maxit=30)
         rec["rho_A"], rec["cycles"] = round(rho, 5), ncyc
         xs = torch.zeros(N, dtype=torch.float64, device=dev)
         chf.pcg_solve(H, bd, xs, rtol=1e-8, maxit=200, raise_on_noconv=False)
@@ -319,7 +317,7 @@ def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
             chf.levels_setup(H, degree=k, pattern=1, tmax=args.tmax, v0=v0)
             torch.cuda.synchronize()
             rec[f"levels_setup_ms_{name}"] = round(1e3 * (time.perf_counter() - t), 1)
-            rho, cyc = learned.energy_factor(H, Aq, e0)
+            rho, cyc = chf.levels_energy_factor(H, e0)
             rec[f"rho_A_{name}"] = round(rho, 5)
             rec[f"cycles_{name}"] = cyc
             H.destroy()

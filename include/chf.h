@@ -93,12 +93,15 @@ int chf_pattern_lower(chf_bsr A, chf_pattern* out);
  * unless lower triangular, strictly ascending per row, diagonal present. */
 int chf_pattern_from_csr(int64_t nb, const int64_t* rowptr, const int32_t* colidx,
                          chf_pattern* out);
-/* Adaptive block-FSAI pattern (Algorithm 1, Lemma 2.4) from P0 = diagonal,
- * computed on the GPU. tmax >= 0 adaptive steps; tau in (0, 1]. A candidate
- * c < k with structurally nonzero (FA)_kc enters row k when
- * g* = -log rho_c* > -log tau + 1e-12; ties within a relative 1e-9 of g* go to
- * the smallest column. Blocks per row are limited to tmax+1 <= 32. */
-int chf_pattern_adaptive(chf_bsr A, int tmax, double tau, chf_pattern* out);
+/* Adaptive block-FSAI pattern (Algorithm 1, Lemma 2.4), computed on the GPU.
+ * P0: the initial pattern of Algorithm 1 (borrowed, same block count as A;
+ * NULL = the diagonal, the choice of Sec. 5). tmax >= 0 adaptive steps after
+ * P0; tau in (0, 1]. A candidate c < k, c not in P_k, with structurally
+ * nonzero (FA)_kc enters row k when g* = -log rho_c* > -log tau + 1e-12; ties
+ * within a relative 1e-9 of g* go to the smallest column. The longest row of
+ * P0 plus tmax must not exceed 32 blocks (EINVAL). ENOTSPD if a local matrix
+ * is not positive definite. tmax = 0 returns a copy of P0. */
+int chf_pattern_adaptive(chf_bsr A, chf_pattern P0, int tmax, double tau, chf_pattern* out);
 int chf_pattern_info(chf_pattern P, int64_t* nb, int64_t* nnz);
 int chf_pattern_export(chf_pattern P, int64_t* rowptr, int32_t* colidx);
 int chf_pattern_destroy(chf_pattern P);
@@ -222,6 +225,15 @@ int chf_levels_set_cycle(chf_levels L, chf_smoother smoother, double param, chf_
 /* One cycle (V(k,k), or V(2k,0) when so set) on level 0: x <- V(b, x);
  * vectors of the hierarchy's working dtype (double for F64, float otherwise). */
 int chf_vcycle(chf_levels L, const void* b, void* x, int x_is_zero, hipStream_t stream);
+/* Energy-norm convergence factor of the cycle as a stationary iteration on
+ * A x = 0 (Ex. 5.1's rho_A, with b = 0): e <- cycle(0, e) from e0 until
+ * ||e||_A < tol ||e0||_A or maxit cycles (maxit >= 1, tol >= 0);
+ * *rho = (e_n^T A e_n / e0^T A e0)^{1/(2n)} and *cycles = n. e0: device
+ * double[N] on level 0, not modified; a mixed hierarchy cycles in FP32 on e0
+ * rounded, and every energy norm is formed in FP64 with the FP64 A.
+ * Synchronises `stream` once per cycle. */
+int chf_levels_energy_factor(chf_levels L, const double* e0, double tol, int maxit, double* rho, int* cycles,
+                             hipStream_t stream);
 /* FP64 PCG from x = 0 with one cycle as preconditioner (cast to and from
  * the working dtype for mixed hierarchies). Stops when the recursive
  * residual ||r|| <= rtol ||b||. flexible != 0: Polak-Ribiere beta (required,

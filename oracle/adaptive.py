@@ -152,11 +152,14 @@ def adaptive_row(a: Bsr, k: int, tmax: int, tau: float = 1.0, p0=None,
     return pk
 
 
-def adaptive_pattern(a: Bsr, tmax: int, tau: float = 1.0, rows=None, **kw):
-    """Algorithm 1 for all rows (or the listed ones): CSR of final patterns."""
+def adaptive_pattern(a: Bsr, tmax: int, tau: float = 1.0, rows=None, p0_pattern=None, **kw):
+    """Algorithm 1 for all rows (or the listed ones): CSR of final patterns.
+    p0_pattern: the initial pattern P0 as CSR (prow, pcol); None = diagonal."""
     rows = range(a.nb) if rows is None else rows
     prow, pcol = [0], []
     for k in rows:
-        pcol.extend(adaptive_row(a, int(k), tmax, tau, **kw))
+        k = int(k)
+        p0 = None if p0_pattern is None else p0_pattern[1][p0_pattern[0][k]:p0_pattern[0][k + 1]]
+        pcol.extend(adaptive_row(a, k, tmax, tau, p0=p0, **kw))
         prow.append(len(pcol))
     return np.array(prow, dtype=np.int64), np.array(pcol, dtype=np.int64)

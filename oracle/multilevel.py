@@ -29,12 +29,45 @@ def block_prolongator(p_s: sp.csr_matrix, b: int, basis=None) -> sp.csr_matrix:
 
 
 def galerkin(a: Bsr, p_s: sp.csr_matrix, basis=None) -> Bsr:
-    """A_c = P^T A P with P = T (P_s (x) I_b)."""
-    pb = block_prolongator(p_s, a.b, basis)
-    ac = pb.T @ a.scipy().tocsr() @ pb
-    ac = sp.csr_matrix(ac)
-    ac.sort_indices()
-    return from_scipy(ac, a.b)
+    """A_c = P^T A P with P = T (P_s (x) I_b), written block by block:
+
+        (A_c)_IJ = sum_i sum_j (P_s)_iI (P_s)_jJ  T_i^T A_ij T_j.
+
+    The congruence T_i^T A_ij T_j is formed for every stored block; the double
+    sum with the scalar weights is the same for each of the b*b positions of
+    a block, so it is evaluated as the scalar sparse product P_s^T X P_s of
+    the matrix X holding that position of every block. The block pattern of
+    A_c is the structural product struct(P_s^T struct(A) P_s): blocks that
+    cancel to zero stay stored."""
+    b = a.b
+    nb = a.nb
+    rows = np.repeat(np.arange(nb), np.diff(a.rowptr))
+    cols = np.asarray(a.colidx, dtype=np.int64)
+    vals = np.asarray(a.vals, dtype=np.float64)
+    if basis is not None:
+        t = np.asarray(basis, dtype=np.float64)
+        cong = np.empty_like(vals)
+        step = 1 << 18
+        for s0 in range(0, len(cols), step):
+            s1 = min(s0 + step, len(cols))
+            cong[s0:s1] = np.swapaxes(t[rows[s0:s1]], 1, 2) @ vals[s0:s1] @ t[cols[s0:s1]]
+        vals = cong
+    ps = sp.csr_matrix(p_s, dtype=np.float64)
+    nc = ps.shape[1]
+    ones_a = sp.csr_matrix((np.ones(len(cols)), cols, a.rowptr), shape=(nb, nb))
+    ones_p = sp.csr_matrix((np.ones(ps.nnz), ps.indices, ps.indptr), shape=ps.shape)
+    struct = sp.csr_matrix(ones_p.T @ ones_a @ ones_p)
+    struct.sort_indices()
+    srows = np.repeat(np.arange(nc, dtype=np.int64), np.diff(struct.indptr))
+    key = srows * nc + struct.indices
+    out = np.zeros((struct.nnz, b, b))
+    for r in range(b):
+        for c in range(b):
+            x = sp.csr_matrix((vals[:, r, c], cols, a.rowptr), shape=(nb, nb))
+            prod = sp.coo_matrix(ps.T @ x @ ps)
+            pos = np.searchsorted(key, prod.row.astype(np.int64) * nc + prod.col)
+            out[pos, r, c] = prod.data
+    return Bsr(struct.indptr.astype(np.int64), struct.indices.astype(np.int64), out, b)
 
 
 @dataclass

@@ -16,6 +16,7 @@ __all__ = [
     "cheb4_smooth", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
     "levels_set_beta", "levels_set_cycle", "levels_set_nesting", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
+    "levels_energy_factor",
     "bicgstab_solve",
     "mlp_candidates", "mlp_features", "mlp_create", "mlp_get_params", "mlp_forward",
     "mlp_loss_grad", "mlp_train_step", "mlp_propose", "mlp_labels", "mlp_train",
@@ -51,7 +52,7 @@ EXPORTED = {
     "chf_bsr_spmv": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, C.c_int, _vp]),
     "chf_pattern_lower": (C.c_int, [_vp, C.POINTER(_vp)]),
     "chf_pattern_from_csr": (C.c_int, [_i64, _vp, _vp, C.POINTER(_vp)]),
-    "chf_pattern_adaptive": (C.c_int, [_vp, C.c_int, _dbl, C.POINTER(_vp)]),
+    "chf_pattern_adaptive": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.POINTER(_vp)]),
     "chf_pattern_info": (C.c_int, [_vp, _pi64, _pi64]),
     "chf_pattern_export": (C.c_int, [_vp, _vp, _vp]),
     "chf_pattern_destroy": (C.c_int, [_vp]),
@@ -79,6 +80,7 @@ EXPORTED = {
     "chf_levels_set_beta": (C.c_int, [_vp, C.c_int, _dbl]),
     "chf_vcycle": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp]),
     "chf_pcg_solve": (C.c_int, [_vp, _vp, _vp, _dbl, C.c_int, C.c_int, _pint, _vp, _pd, _vp]),
+    "chf_levels_energy_factor": (C.c_int, [_vp, _vp, _dbl, C.c_int, _pd, _pint, _vp]),
     "chf_mlp_candidates": (C.c_int, [_vp, _pi64, _vp, _vp]),
     "chf_mlp_features": (C.c_int, [_vp, _i32, _i32, _vp, _vp]),
     "chf_mlp_create": (C.c_int, [_vp, C.POINTER(_vp)]),
@@ -245,9 +247,10 @@ def pattern_from_csr(nb, rowptr, colidx) -> Pattern:
     return Pattern(out)
 
 
-def pattern_adaptive(A: Bsr, tmax: int, tau: float = 1.0) -> Pattern:
+def pattern_adaptive(A: Bsr, tmax: int, tau: float = 1.0, p0: Pattern | None = None) -> Pattern:
     out = C.c_void_p()
-    _check(_fn("chf_pattern_adaptive")(A.h, int(tmax), float(tau), C.byref(out)))
+    _check(_fn("chf_pattern_adaptive")(A.h, p0.h if p0 is not None else None, int(tmax), float(tau),
+                                       C.byref(out)))
     return Pattern(out)
 
 
@@ -394,6 +397,15 @@ def levels_set_cycle(L: Levels, smoother=SMOOTH_CHEB4, param=0.0, cycle=CYCLE_VK
 
 def vcycle(L: Levels, b, x, x_is_zero=True, stream=None):
     _check(_fn("chf_vcycle")(L.h, _ptr(b), _ptr(x), int(bool(x_is_zero)), _stream(stream)))
+
+
+def levels_energy_factor(L: Levels, e0, tol=1e-8, maxit=50, stream=None):
+    """Returns (rho_A, cycles) of the hierarchy's cycle from the error e0
+    (device double[N], not modified)."""
+    rho, cyc = C.c_double(), C.c_int()
+    _check(_fn("chf_levels_energy_factor")(L.h, _ptr(e0), float(tol), int(maxit), C.byref(rho), C.byref(cyc),
+                                           _stream(stream)))
+    return rho.value, cyc.value
 
 
 def pcg_solve(L: Levels, b, x, rtol=1e-8, maxit=200, flexible=False, stream=None, raise_on_noconv=True):

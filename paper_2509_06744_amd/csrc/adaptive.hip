@@ -583,9 +583,16 @@ __device__ inline void ai_init_slots(int k, int b, int s0, int s1, const int* __
     }
 }
 
+// P0 (Algorithm 1's initial pattern): when p0_rowptr is given, the blocks of
+// row k of P0 other than k enter first, in ascending order, through the same
+// bordering update as an adaptive choice (a block that is not yet a candidate
+// is structurally decoupled from the current P~, so its W = A_cc, H_kc = 0 are
+// exact and it is appended as one); the t_max adaptive steps follow.
 template <int MAXB, int BC>
 __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, int cap, const int* __restrict__ a_rowptr,
-                       const int* __restrict__ a_col, const double* __restrict__ a_vals, int* __restrict__ out_cols,
+                       const int* __restrict__ a_col, const double* __restrict__ a_vals,
+                       const int* __restrict__ p0_rowptr, const int* __restrict__ p0_col, int out_stride,
+                       int* __restrict__ out_cols,
                        int* __restrict__ out_cnt, const AiState& S, double* sm, double* gbufs, int* mark,
                        int* plist, int* tmp_a, int* tmp_b, int* sh, int* err) {
     if (BC > 0) b = BC;
@@ -643,9 +650,17 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
     int m = 0;
     bool pending = false;
     int cstar = -1;
+    const int* forced = nullptr;
+    int nforced = 0;
+    if (p0_rowptr) {
+        forced = p0_col + p0_rowptr[k];
+        nforced = p0_rowptr[k + 1] - p0_rowptr[k] - 1;   // the diagonal is the row's last entry
+    }
+    const int total = nforced + tmax;
     #pragma unroll 1
-    for (int step = 0; step < tmax && sh[3]; ++step) {
-        if (ncand == 0) break;
+    for (int step = 0; step < total && sh[3]; ++step) {
+        const bool is_forced = step < nforced;
+        if (ncand == 0 && !is_forced) break;
         #pragma unroll 1
         for (int s0 = 0; s0 < ncand; s0 += NB)
             ai_batch<MAXB, BC>(k, b, s0, min(NB, ncand - s0), pending, cstar, m - 1, a_rowptr, a_col, a_vals, S, S.V,
@@ -655,6 +670,31 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
             if (lane == 0) atomicMin(err, k);
             break;
         }
+        int bs;
+        if (is_forced) {
+            cstar = forced[step];
+            int found = INT_MAX;
+            #pragma unroll 1
+            for (int i = lane; i < ncand; i += 64)
+                if (S.cand[i] == cstar) found = min(found, i);
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) found = min(found, __shfl_xor(found, o, 64));
+            if (found == INT_MAX) {
+                if (ncand >= cap) {
+                    if (lane == 0) { atomicMin(err, k); sh[3] = 0; }
+                    __syncthreads();
+                    break;
+                }
+                if (lane == 0) {
+                    S.cand[ncand] = cstar;
+                    S.nzn[ncand] = 0;
+                }
+                __syncthreads();
+                ai_init_slots(k, b, ncand, ncand + 1, a_rowptr, a_col, a_vals, S, tmp_a, tmp_b);
+                found = ncand++;
+            }
+            bs = found;
+        } else {
         // selection: largest gain; ties within a relative AD_TIE_REL of it go
         // to the smallest block index
         double gm = -1e300;
@@ -670,9 +710,10 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) best = min(best, (long long)__shfl_xor(best, o, 64));
         if (!(gm > thresh)) break;
-        const int bs = (int)(best & 0xffffffffLL);
+        bs = (int)(best & 0xffffffffLL);
         cstar = (int)(best >> 32);
-        if (step == tmax - 1) {
+        }
+        if (step == total - 1) {
             if (lane == 0) plist[m] = cstar;
             ++m;
             pending = false;
@@ -870,7 +911,7 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
             tmp[j + 1] = v;
         }
         #pragma unroll 1
-        for (int i = 0; i <= m; ++i) out_cols[(int64_t)k * (tmax + 1) + i] = tmp[i];
+        for (int i = 0; i <= m; ++i) out_cols[(int64_t)k * out_stride + i] = tmp[i];
         out_cnt[k] = m + 1;
     }
     __syncthreads();
@@ -879,7 +920,9 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
 template <int MAXB, int BC>
 __global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, double thresh, int cap,
                                                  const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
-                                                 const double* __restrict__ a_vals, int* __restrict__ out_cols,
+                                                 const double* __restrict__ a_vals, const int* __restrict__ p0_rowptr,
+                                                 const int* __restrict__ p0_col, int out_stride,
+                                                 int* __restrict__ out_cols,
                                                  int* __restrict__ out_cnt, int kinv_lds, int v_lds, int Mmax,
                                                  int maxrow, double* scratch, int64_t gstride, int* counter,
                                                  int* err) {
@@ -927,33 +970,46 @@ __global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, do
         const int64_t row = next;
         __syncthreads();
         if (row >= nb) break;
-        ai_row<MAXB, BC>((int)row, b, tmax, thresh, cap, a_rowptr, a_col, a_vals, out_cols, out_cnt, S, sm, gbufs, mark,
-                         plist, tmp_a, tmp_b, sh, err);
+        ai_row<MAXB, BC>((int)row, b, tmax, thresh, cap, a_rowptr, a_col, a_vals, p0_rowptr, p0_col, out_stride,
+                         out_cols, out_cnt, S, sm, gbufs, mark, plist, tmp_a, tmp_b, sh, err);
     }
 }
 
 template <int MAXB, int BC>
 static void ai_launch(int64_t grid, size_t dyn, hipStream_t s, int64_t nb, int b, int tmax, double thresh, int cap,
-                      chf_bsr A, int* out_cols, int* out_cnt, int kinv_lds, int v_lds, int Mmax, int maxrow,
-                      double* scratch, int64_t stride, int* counter, int* err) {
+                      chf_bsr A, const int* p0_rowptr, const int* p0_col, int out_stride, int* out_cols, int* out_cnt,
+                      int kinv_lds, int v_lds, int Mmax, int maxrow, double* scratch, int64_t stride, int* counter,
+                      int* err) {
     auto kern = k_adaptive<MAXB, BC>;
     if (dyn > 64 * 1024)
         CHF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), dyn, s, nb, b, tmax, thresh, cap,
-                       A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, out_cols, out_cnt, kinv_lds, v_lds, Mmax, maxrow,
-                       scratch, stride, counter, err);
+                       A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, p0_rowptr, p0_col, out_stride, out_cols, out_cnt,
+                       kinv_lds, v_lds, Mmax, maxrow, scratch, stride, counter, err);
     CHF_LAUNCH_CHECK();
 }
 
-chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_t s) {
-    CHF_CHECK(tmax >= 0 && tmax + 1 <= AD_MAXP, CHF_EINVAL, "tmax must be in [0, 31]");
+chf_pattern_s* adaptive_pattern_impl(chf_bsr A, const chf_pattern_s* P0, int tmax, double tau, hipStream_t s) {
     CHF_CHECK(tau > 0.0 && tau <= 1.0, CHF_EINVAL, "tau must be in (0, 1]");
     const int64_t nb = A->nb;
     const int b = A->b;
+    int maxp0 = 1;   // blocks per row of P0 (diagonal when P0 is NULL)
+    if (P0) {
+        CHF_CHECK(P0->nb == nb, CHF_EINVAL, "P0 has a different number of block rows than A");
+        for (int64_t k = 0; k < nb; ++k) maxp0 = (int)std::max<int64_t>(maxp0, P0->rowptr[k + 1] - P0->rowptr[k]);
+    }
+    CHF_CHECK(tmax >= 0 && (int64_t)maxp0 + tmax <= AD_MAXP, CHF_EINVAL,
+              "tmax plus the longest row of P0 must not exceed 32 blocks");
+    const int width = maxp0 + tmax;   // blocks per output row at most
     std::unique_ptr<chf_pattern_s> P(new chf_pattern_s);
     P->nb = nb;
     P->rowptr.assign(nb + 1, 0);
     if (tmax == 0 || nb == 0) {
+        if (P0) {
+            P->rowptr = P0->rowptr;
+            P->colidx = P0->colidx;
+            return P.release();
+        }
         for (int64_t k = 0; k < nb; ++k) {
             P->colidx.push_back((int32_t)k);
             P->rowptr[k + 1] = k + 1;
@@ -964,8 +1020,19 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     // every candidate lies in the union of the rows A_j, j in P_k
     int64_t maxrow = 1;
     for (int64_t k = 0; k < nb; ++k) maxrow = std::max<int64_t>(maxrow, A->rowptr[k + 1] - A->rowptr[k]);
-    const int cap = (int)std::min<int64_t>((int64_t)(tmax + 1) * maxrow, 1 << 20);
-    const int Mmax = (tmax - 1) * b;   // Kinv and V never grow past t_max - 1 blocks
+    const int cap = (int)std::min<int64_t>((int64_t)width * maxrow, 1 << 20);
+    // Kinv and V never grow past width - 2 blocks (the last block enters
+    // without a bordering update)
+    const int Mmax = std::max(1, width - 2) * b;
+    DevBuf<int> d_p0_rowptr, d_p0_col;
+    if (P0) {
+        std::vector<int> rp(nb + 1);
+        for (int64_t k = 0; k <= nb; ++k) rp[k] = (int)P0->rowptr[k];
+        d_p0_rowptr.alloc(nb + 1);
+        d_p0_rowptr.upload(rp.data(), nb + 1, s);
+        d_p0_col.alloc(std::max<size_t>(1, P0->colidx.size()));
+        d_p0_col.upload(P0->colidx.data(), P0->colidx.size(), s);
+    }
     int dev = 0, lim = 0;
     CHF_HIP(hipGetDevice(&dev));
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -991,7 +1058,7 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     const int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, nb);
     const int64_t stride = (ai_global_doubles(Mmax, b, cap, !kinv_lds, !v_lds) + 31) / 32 * 32;
     DevBuf<double> scratch((size_t)grid * stride);
-    DevBuf<int> out_cols((size_t)nb * (tmax + 1)), out_cnt(nb), flags(2);
+    DevBuf<int> out_cols((size_t)nb * width), out_cnt(nb), flags(2);
     int init[2] = {0, INT32_MAX};
     flags.upload(init, 2, s);
     const double thresh = -std::log(tau) + AD_GAIN_EPS;
@@ -999,7 +1066,8 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     // the block sizes of the workloads get their own instantiation (block
     // offsets are compile-time constants); others share one per size class
 #define CHF_AI_LAUNCH(MB, BCV)                                                                                   \
-    ai_launch<MB, BCV>(grid, dyn, s, nb, b, tmax, thresh, cap, A, out_cols.p, out_cnt.p, ki, vi, Mmax, (int)maxrow, \
+    ai_launch<MB, BCV>(grid, dyn, s, nb, b, tmax, thresh, cap, A, P0 ? d_p0_rowptr.p : nullptr,                  \
+                       P0 ? d_p0_col.p : nullptr, width, out_cols.p, out_cnt.p, ki, vi, Mmax, (int)maxrow,       \
                        scratch.p, stride, flags.p, flags.p + 1)
     if (b == 10) CHF_AI_LAUNCH(10, 10);
     else if (b == 21) CHF_AI_LAUNCH(21, 21);
@@ -1009,7 +1077,7 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
     else if (b <= 21) CHF_AI_LAUNCH(21, 0);
     else CHF_AI_LAUNCH(32, 0);
 #undef CHF_AI_LAUNCH
-    std::vector<int> hcols((size_t)nb * (tmax + 1)), hcnt(nb);
+    std::vector<int> hcols((size_t)nb * width), hcnt(nb);
     int hflags[2];
     out_cols.download(hcols.data(), hcols.size(), s);
     out_cnt.download(hcnt.data(), nb, s);
@@ -1019,18 +1087,18 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_
         fail(CHF_ENOTSPD, "adaptive pattern: local matrices of block row " + std::to_string(hflags[1]) +
                               " are not positive definite");
     for (int64_t k = 0; k < nb; ++k) {
-        CHF_CHECK(hcnt[k] >= 1 && hcnt[k] <= tmax + 1, CHF_EDEVICE, "adaptive pattern: bad row count");
-        for (int i = 0; i < hcnt[k]; ++i) P->colidx.push_back(hcols[(size_t)k * (tmax + 1) + i]);
+        CHF_CHECK(hcnt[k] >= 1 && hcnt[k] <= width, CHF_EDEVICE, "adaptive pattern: bad row count");
+        for (int i = 0; i < hcnt[k]; ++i) P->colidx.push_back(hcols[(size_t)k * width + i]);
         P->rowptr[k + 1] = (int64_t)P->colidx.size();
     }
     return P.release();
 }
 }  // namespace chf
 
-extern "C" int chf_pattern_adaptive(chf_bsr A, int tmax, double tau, chf_pattern* out) {
+extern "C" int chf_pattern_adaptive(chf_bsr A, chf_pattern P0, int tmax, double tau, chf_pattern* out) {
     return chf::guarded([&] {
         CHF_CHECK(A && out, CHF_EINVAL, "NULL argument");
-        *out = chf::adaptive_pattern_impl(A, tmax, tau, 0);
+        *out = chf::adaptive_pattern_impl(A, P0, tmax, tau, 0);
     });
 }
 

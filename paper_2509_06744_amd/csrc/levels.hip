@@ -26,7 +26,7 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
 chf_bsr_s* bsr_triple_impl(chf_bsr A, const chf_fsai_s& G, hipStream_t s);
 void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const double* v0, double safety,
                   double* beta_out, double* theta_out, hipStream_t s);
-chf_pattern_s* adaptive_pattern_impl(chf_bsr A, int tmax, double tau, hipStream_t s);
+chf_pattern_s* adaptive_pattern_impl(chf_bsr A, const chf_pattern_s* P0, int tmax, double tau, hipStream_t s);
 void validate_pattern(int64_t nb, const int64_t* rowptr, const int32_t* colidx);
 
 // ------------------------------------------------- host structure products --
@@ -813,7 +813,7 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
             if (L.preset) {
                 // caller-supplied pattern (e.g. a learned proposal)
             } else if (opts->pattern == 1) {
-                L.P = adaptive_pattern_impl(L.A, opts->tmax, opts->tau, st);
+                L.P = adaptive_pattern_impl(L.A, nullptr, opts->tmax, opts->tau, st);
             } else {
                 chf_pattern P = nullptr;
                 int rc = opts->pattern == 0 ? chf_pattern_lower(L.A, &P) : CHF_OK;
@@ -833,7 +833,7 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
                 // Algorithm 1's pattern (same t_max and tau)
                 L.G0 = fsai_setup_impl(L.A, *L.P, opts->dtype, br, st);
                 std::unique_ptr<chf_bsr_s> A1(bsr_triple_impl(L.A, *L.G0, st));
-                L.P1 = adaptive_pattern_impl(A1.get(), opts->tmax, opts->tau, st);
+                L.P1 = adaptive_pattern_impl(A1.get(), nullptr, opts->tmax, opts->tau, st);
                 L.G1 = fsai_setup_impl(A1.get(), *L.P1, opts->dtype, br, st);
                 L.G = new chf_fsai_s;
                 L.G->nb = L.G0->nb;
@@ -1008,6 +1008,55 @@ extern "C" int chf_levels_set_cycle(chf_levels H, chf_smoother smoother, double 
         H->smoother = smoother;
         H->sm_param = param;
         H->cycle = cycle;
+    });
+}
+
+extern "C" int chf_levels_energy_factor(chf_levels H, const double* e0, double tol, int maxit, double* rho,
+                                        int* cycles, hipStream_t stream) {
+    return guarded([&] {
+        check_ready(H);
+        CHF_CHECK(e0 && rho && maxit >= 1 && tol >= 0, CHF_EINVAL, "bad argument");
+        hipStream_t s = stream;
+        chf_level_s& L0 = H->lev[0];
+        const int64_t n = L0.A->nb * (int64_t)L0.A->b;
+        if (H->pcg_n != n) {
+            H->pcg_buf.alloc((size_t)std::max<int64_t>(1, 6 * n));
+            H->scal.alloc(8);
+            H->part.alloc(RED_BLOCKS);
+            H->pcg_n = n;
+        }
+        double* e64 = H->pcg_buf.p;        // the error in FP64
+        double* ae = e64 + n;              // A e
+        void* ew = e64 + 2 * n;            // the error in the working dtype
+        void* zw = e64 + 3 * n;            // zero right-hand side, working dtype
+        double* sc = H->scal.p;
+        const Sell& A64 = L0.A->sell(CHF_F64, s);
+        const bool mixed = H->vec != CHF_F64;
+        fill_zero(zw, n * vec_size(H->vec), s);
+        cast_vec(CHF_F64, e0, H->vec, mixed ? ew : (void*)e64, n, s);
+        // e^T A e of the current iterate, in FP64
+        auto energy = [&]() {
+            if (mixed) cast_vec(H->vec, ew, CHF_F64, e64, n, s);
+            sell_spmv(A64, CHF_F64, e64, ae, nullptr, EPI_AX, nullptr, nullptr, 0, 0, s);
+            dot(CHF_F64, e64, ae, n, sc, H->part.p, s);
+            double v;
+            CHF_HIP(hipMemcpyAsync(&v, sc, 8, hipMemcpyDeviceToHost, s));
+            CHF_HIP(hipStreamSynchronize(s));
+            return v;
+        };
+        const double en0 = energy();
+        CHF_CHECK(std::isfinite(en0) && en0 > 0, CHF_EINVAL, "e0 must be nonzero and finite");
+        double en = en0;
+        int cyc = 0;
+        while (cyc < maxit) {
+            vcycle_rec(*H, 0, zw, mixed ? ew : (void*)e64, false, s);
+            ++cyc;
+            en = energy();
+            CHF_CHECK(std::isfinite(en), CHF_EBREAKDOWN, "energy norm of the error is not finite");
+            if (std::sqrt(en / en0) < tol) break;
+        }
+        *rho = std::pow(en / en0, 1.0 / (2.0 * cyc));
+        if (cycles) *cycles = cyc;
     });
 }
 

@@ -29,23 +29,3 @@ def train(X, Y, params0, perm, epochs=4, batch=8192, lr=2e-3):
     net = chf.mlp_create(params0)
     hist = chf.mlp_train(net, X, Y, Y.shape[0], perm, batch=batch, epochs=epochs, lr=lr)
     return net, hist
-
-
-def energy_factor(L, A, e0, tol=1e-8, maxit=50):
-    """V-cycle convergence factor in the energy norm: iterate e <- V(0, e)
-    until ||e||_A < tol ||e0||_A or maxit cycles; returns (rho_A, cycles)."""
-    e = e0.clone()
-    zero = torch.zeros_like(e)
-    ae = torch.empty_like(e)
-    chf.bsr_spmv(A, e, ae)
-    en0 = float(torch.dot(e, ae))
-    en = en0
-    n = 0
-    while n < maxit:
-        chf.vcycle(L, zero, e, x_is_zero=False)
-        n += 1
-        chf.bsr_spmv(A, e, ae)
-        en = float(torch.dot(e, ae))
-        if (en / en0) ** 0.5 < tol:
-            break
-    return (en / en0) ** (1.0 / (2 * n)), n

@@ -36,3 +36,13 @@ def test_library_exports_every_declared_symbol():
 def test_version_string():
     import paper_2509_06744_amd as chf
     assert "gfx950" in chf.version()
+
+
+def test_binding_exports_every_wrapper():
+    # every public wrapper defined in the binding is re-exported by the package
+    import inspect
+
+    from paper_2509_06744_amd import binding
+    defined = {n for n, f in vars(binding).items()
+               if inspect.isfunction(f) and not n.startswith("_") and f.__module__ == binding.__name__}
+    assert defined <= set(binding.__all__), sorted(defined - set(binding.__all__))

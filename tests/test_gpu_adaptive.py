@@ -35,6 +35,46 @@ def test_adaptive_pattern_bit_exact(chf, n, dim, b, pw, tmax):
     assert np.array_equal(pcol, ocol)
 
 
+@pytest.mark.parametrize("n,dim,b,pw,tmax", [(11, 2, 10, 2, 4), (9, 2, 3, 2, 6), (5, 3, 10, 2, 3), (7, 2, 21, 3, 4),
+                                               (8, 2, 10, 2, 0)])
+def test_adaptive_pattern_from_lower_p0(chf, n, dim, b, pw, tmax):
+    """Algorithm 1 started from P0 = lower(A) instead of the diagonal."""
+    from oracle import fsai
+    p = make_problem(n, dim, b, pw, seed=0)
+    a = from_problem(p)
+    p0 = fsai.pattern_lower(a)
+    orow, ocol = adaptive.adaptive_pattern(a, tmax, p0_pattern=p0)
+    A = upload(p)
+    P = chf.pattern_adaptive(A, tmax, p0=chf.pattern_lower(A))
+    prow, pcol = chf.pattern_export(P)
+    assert np.array_equal(prow, orow)
+    assert np.array_equal(pcol, ocol)
+
+
+def test_adaptive_pattern_p0_with_decoupled_blocks(chf):
+    """P0 rows holding blocks far from row k (no coupling with k or with the
+    rest of P0): they enter as decoupled candidates."""
+    p = make_problem(10, 2, 3, 2, seed=1)
+    a = from_problem(p)
+    rng = np.random.default_rng(4)
+    rowptr, cols = [0], []
+    for k in range(p.nb):
+        extra = sorted(set(int(c) for c in rng.integers(0, k, 2))) if k > 30 else []
+        cols.extend(extra + [k])
+        rowptr.append(len(cols))
+    p0 = (np.array(rowptr, dtype=np.int64), np.array(cols, dtype=np.int64))
+    orow, ocol = adaptive.adaptive_pattern(a, 5, p0_pattern=p0)
+    A = upload(p)
+    P0 = chf.pattern_from_csr(p.nb, p0[0], p0[1].astype(np.int32))
+    P = chf.pattern_adaptive(A, 5, p0=P0)
+    prow, pcol = chf.pattern_export(P)
+    assert np.array_equal(prow, orow)
+    assert np.array_equal(pcol, ocol)
+    with pytest.raises(chf.ChfError) as ei:      # 3 blocks of P0 + 30 steps > 32
+        chf.pattern_adaptive(A, 30, p0=P0)
+    assert ei.value.code == -1
+
+
 def test_adaptive_rotation_invariant_seeds(chf):
     # the pattern of R^T (D (x) I) R does not depend on the seed of R
     pats = []

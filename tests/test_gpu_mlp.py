@@ -149,6 +149,6 @@ def test_learned_pattern_gain_over_adaptive(chf):
     for name, P in [("adaptive", Pa), ("learned", Pl)]:
         # level 0 takes the given pattern, coarser levels Algorithm 1 (t_max 8)
         A0, L, _, _ = gpu_levels(p, 4, 4, 1, tmax=8, level0_pattern=P)
-        rho[name], _ = learned.energy_factor(L, A0, e0)
+        rho[name], _ = chf.levels_energy_factor(L, e0)
     print(f"pattern time adaptive {t_ad * 1e3:.1f} ms, learned {t_ml * 1e3:.1f} ms; rho_A {rho}")
     assert rho["learned"] <= 1.10 * rho["adaptive"]

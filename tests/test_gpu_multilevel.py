@@ -125,3 +125,36 @@ def test_error_coarsest_not_spd_reports_minus_two(chf, levels):
     with pytest.raises(chf.ChfError) as ei:
         chf.levels_setup(L, degree=2, pattern=0, v0=[dev(s) for s in starts[:-1]])
     assert ei.value.code == -3 and ei.value.bad_row == -2
+
+
+def test_pcg_breakdown_keeps_last_iterate(chf):
+    """Bounds beta_l ten times too small make the smoother's polynomial blow up
+    on the upper spectrum, so the cycle is indefinite and r^T z < 0 at the
+    first step (the oracle gives about -6e9 here): PCG reports CHF_EBREAKDOWN
+    and leaves x at its start, zero."""
+    import torch
+    p = make_problem(16, 2, 3, 2, seed=2)
+    A, L, _, _ = gpu_levels(p, 3, 2, 0, seed=2)
+    for l in range(2):
+        chf.levels_set_beta(L, l, 0.1 * chf.levels_get_beta(L, l))
+    x = torch.full((p.ndof,), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(chf.ChfError) as ei:
+        chf.pcg_solve(L, dev(rhs(2, p.ndof)), x, rtol=1e-8, maxit=50)
+    assert ei.value.code == -6
+    assert not torch.any(x != 0)
+
+
+def test_energy_factor_matches_oracle(chf):
+    """chf_levels_energy_factor against the oracle's protocol (same bounds):
+    a fixed number of cycles (tol 0), then to the tolerance."""
+    from problems import uniform_start
+    p = make_problem(16, 2, 3, 2, seed=0)
+    olv = _oracle_levels(p, 3)
+    betas = [lv.beta for lv in olv[:-1]]
+    A, L, _, _ = gpu_levels(p, 3, 3, 0, betas=betas)
+    e0 = uniform_start(0, p.ndof)
+    for tol, maxit in [(0.0, 6), (1e-8, 50)]:
+        want, wn = multilevel.energy_factor(olv, e0, 3, tol=tol, maxit=maxit)
+        rho, n = chf.levels_energy_factor(L, dev(e0), tol=tol, maxit=maxit)
+        assert n == wn
+        assert abs(rho - want) < 1e-9 * want
