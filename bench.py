@@ -32,6 +32,28 @@ TRAFFIC_NOTE = os.path.join(ROOT, "profiles", "k_sell_spmv_residual_512x512_b10_
 SPMV_SOURCE = os.path.join(ROOT, "paper_2509_06744_amd", "csrc", "bsr.hip")
 
 
+KERNEL_STATS = os.path.join(ROOT, "profiles", "bench_512x512_b10_kernel_stats.md")
+GOLDEN_C1 = os.path.join(ROOT, "tests", "golden", "c1_pcg_iterations.json")
+
+
+def rocprof_residual_avg_ms():
+    """rocprofv3's average duration of the timed residual SpMV dispatches from
+    the committed kernel-statistics summary, or None when the SpMV source
+    changed since it was taken."""
+    import hashlib
+    try:
+        note = open(KERNEL_STATS).read()
+        sha = hashlib.sha256(open(SPMV_SOURCE, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f"sha256 prefix {sha}" not in note:
+        return None
+    for line in note.splitlines():
+        if line.startswith("rocprof_timed_avg_us:"):
+            return float(line.split(":", 1)[1]) / 1e3
+    return None
+
+
 def measured_traffic():
     """HBM bytes per launch of the residual SpMV from the committed counter
     summary, or None when the kernel source changed since it was measured."""
@@ -445,6 +467,23 @@ def main():
     log(f"smoother: {ms_app:.3f} ms/application, {gdofs:.3f} GDOF/s, "
         f"{b_app / (ms_app * 1e-3) / 1e9:.0f} GB/s algorithmic")
 
+    # the same application timed call by call (median of 20 event pairs), with
+    # x != 0 and with x0 = 0 (one product with A and 5 N vector values fewer)
+    def median_ms(x_is_zero, reps=20):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for _ in range(3):
+            chf.cheb4_smooth(A, G0, beta0, k, bd, x, x_is_zero=x_is_zero, work=work)
+        for a_, b_ in evs:
+            a_.record(stream)
+            chf.cheb4_smooth(A, G0, beta0, k, bd, x, x_is_zero=x_is_zero, work=work)
+            b_.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
+    med_x = median_ms(False)
+    med_0 = median_ms(True)
+    b_app0 = b_app - (nnzb * (b * b * s + 4) + 5 * N * s)
+    log(f"smoother medians: x != 0 {med_x:.3f} ms, x0 = 0 {med_0:.3f} ms")
+
     # ---- dominant kernel: the A residual SpMV r = b - A x, timed alone
     r = torch.empty_like(x)
     for _ in range(3):
@@ -487,12 +526,20 @@ def main():
             "achieved_GBs": round(b_app / (ms_app * 1e-3) / 1e9, 1),
             "hbm_frac": round(b_app / (ms_app * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "wall_s_timed_region": round(t_wall, 4),
+            "median_ms_per_application_20_calls": round(med_x, 5),
+            "median_hbm_frac": round(b_app / (med_x * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "x0_zero": {"median_ms_per_application_20_calls": round(med_0, 5),
+                        "algorithmic_bytes_per_application": b_app0,
+                        "hbm_frac": round(b_app0 / (med_0 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         },
         "roofline": {
             "kernel": "k_sell_spmv<10,double,double,EPI_RES> (r = b - A x, level 0)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
             "avg_launch_ms": round(ms_k1, 5), "algorithmic_bytes_per_launch": bytes_k1,
+            "rocprof_avg_launch_ms": rocprof_residual_avg_ms(),
+            "rocprof_frac": (round(bytes_k1 / (rocprof_residual_avg_ms() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                             if rocprof_residual_avg_ms() else None),
         },
         "setup_fp64": {kk: round(v, 2) for kk, v in setup64.items()},
     }
@@ -544,6 +591,11 @@ def main():
             log(f"PCG {name}: {res[name]}")
             if Hh is not H:
                 Hh.destroy()
+        if n == 512 and L == 6 and k == 4 and args.tmax == 8 and os.path.exists(GOLDEN_C1):
+            gold = json.load(open(GOLDEN_C1))["pcg"]
+            for name in ("fp64", "mixed_f32", "mixed_bf16g"):
+                if name in gold:
+                    res[name]["oracle_iterations"] = gold[name]["iterations"]
         res["mixed_f32_over_fp64_time"] = round(res["mixed_f32"]["time_ms"] / res["fp64"]["time_ms"], 4)
         res["mixed_bf16g_over_fp64_time"] = round(res["mixed_bf16g"]["time_ms"] / res["fp64"]["time_ms"], 4)
         out["pcg"] = res

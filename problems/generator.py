@@ -156,32 +156,76 @@ def pum_block_size(p: int, dim: int) -> int:
     return comb(p + dim, dim)
 
 
-def prolongator_1d(nc: int) -> sp.csr_matrix:
-    """Cell-centred 1D prolongation from nc to 2*nc cells.
+def _lagrange_weights(nodes, t):
+    out = []
+    for i, xi in enumerate(nodes):
+        w = 1.0
+        for j, xj in enumerate(nodes):
+            if j != i:
+                w *= (t - xj) / (xi - xj)
+        out.append(w)
+    return out
 
-    Fine cell 2I+a takes 3/4 of coarse cell I and 1/4 of its neighbour on
-    the same side (I-1 for a = 0, I+1 for a = 1); a neighbour outside the
-    grid is dropped (zero ghost value).
+
+def prolongator_1d(nc: int, order: int = 2, boundary: str = "dirichlet") -> sp.csr_matrix:
+    """Cell-centred 1D interpolation from nc to 2*nc cells.
+
+    In coarse units, fine cell 2I+a sits at t = I - 1/4 (a = 0) or I + 1/4
+    (a = 1). The unscaled Dirichlet Laplacian on the fine grid vanishes half a
+    fine cell beyond its outer cells, i.e. at the coarse coordinates -3/4 and
+    nc - 1/4.
+
+    boundary="dirichlet": the fine value is the Lagrange interpolant through
+    the `order` points nearest to t among the coarse cells and these two
+    boundary points (value 0 there); order 2 is linear (weights 3/4, 1/4 in
+    the interior, 2/3 next to the boundary), order 4 is cubic (interior
+    weights (-5, 35, 105, -7)/128 on I-2..I+1 for a = 0, mirrored for a = 1),
+    exact for polynomials of degree order-1 that vanish at the boundary.
+    boundary="zero_ghost" (order 2 only): 3/4 of cell I and 1/4 of its
+    neighbour on the same side, a neighbour outside the grid dropped.
     """
     nf = 2 * nc
     rows, cols, vals = [], [], []
+    if boundary == "zero_ghost":
+        if order != 2:
+            raise ValueError("zero_ghost is defined for order 2 only")
+        for f in range(nf):
+            big, a = divmod(f, 2)
+            rows.append(f)
+            cols.append(big)
+            vals.append(0.75)
+            other = big - 1 if a == 0 else big + 1
+            if 0 <= other < nc:
+                rows.append(f)
+                cols.append(other)
+                vals.append(0.25)
+        return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+    if boundary != "dirichlet":
+        raise ValueError(boundary)
+    if order < 1 or order > nc + 2:
+        raise ValueError("bad interpolation order")
+    lo, hi = -0.75, nc - 0.25
     for f in range(nf):
         big, a = divmod(f, 2)
-        rows.append(f)
-        cols.append(big)
-        vals.append(0.75)
-        other = big - 1 if a == 0 else big + 1
-        if 0 <= other < nc:
+        t = big - 0.25 if a == 0 else big + 0.25
+        # the order nearest points; no two candidates are equally far from t
+        near = sorted(range(-1, nc + 1), key=lambda i: abs((lo if i < 0 else hi if i >= nc else i) - t))[:order]
+        nodes = sorted(lo if i < 0 else hi if i >= nc else float(i) for i in near)
+        for x, w in zip(nodes, _lagrange_weights(nodes, t)):
+            if x in (lo, hi):
+                continue
             rows.append(f)
-            cols.append(other)
-            vals.append(0.25)
-    return sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+            cols.append(int(x))
+            vals.append(w)
+    m = sp.csr_matrix((vals, (rows, cols)), shape=(nf, nc))
+    m.sort_indices()
+    return m
 
 
-def prolongator(nc: int, dim: int) -> sp.csr_matrix:
+def prolongator(nc: int, dim: int, order: int = 2, boundary: str = "dirichlet") -> sp.csr_matrix:
     """Tensor-product patch prolongator P_s from nc^dim to (2nc)^dim patches
     (scalar weights; the block operator is P_s (x) I_b). x is fastest."""
-    p1 = prolongator_1d(nc)
+    p1 = prolongator_1d(nc, order, boundary)
     p = p1
     for _ in range(dim - 1):
         p = sp.kron(p1, p)

@@ -1,7 +1,10 @@
 """Writes tests/golden/c1_pcg_iterations.json from the oracle alone.
 
 Workload: biharmonic-like 2D problem on 512 x 512 patches, b = 10, seed 0
-(A = R^T (L^2 (x) I_b) R), six-level Galerkin hierarchy, adaptive block-FSAI
+(A = R^T (L^2 (x) I_b) R), six-level Galerkin hierarchy with the bilinear
+patch transfer (--boundary dirichlet, the default: Lagrange interpolation
+with the Dirichlet boundary points as nodes; --boundary zero_ghost: the
+earlier reading with zero ghost cells), adaptive block-FSAI
 on every smoothed level (Algorithm 1, P0 = diagonal, tau = 1, t_max = 8),
 Lanczos bounds (Sec. 5: 100 steps, x 1.01), V(4,4) with fourth-kind Chebyshev
 smoothing, PCG from x = 0 to a recursive relative residual of 1e-8, in three
@@ -122,8 +125,11 @@ def run_pcg(name, apply_a, prec, bvec, flexible, rtol=1e-8, maxit=300):
     return rec
 
 
-def _pcg_worker(args):
-    form, levels, starts, bvec, k = args
+_PCG = None   # (levels, starts, bvec, k), shared with the forked PCG workers
+
+
+def _pcg_worker(form):
+    levels, starts, bvec, k = _PCG
     if form == "fp64":
         return form, run_pcg(form, levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, k), bvec, False), None
     ml = mixed.mixed_levels(levels, "f32" if form == "mixed_f32" else "bf16", starts)
@@ -136,12 +142,13 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--levels", type=int, default=6)
     ap.add_argument("--workers", type=int, default=max(1, min(8, os.cpu_count() or 1) - 1))
+    ap.add_argument("--boundary", default="dirichlet", choices=["dirichlet", "zero_ghost"])
     args = ap.parse_args()
     n, b, tmax, k = args.n, 10, 8, 4
     nl = args.levels
     p = make_problem(n, 2, b, 2, seed=0)
     sizes = grid_sizes(n, nl)
-    pro = [prolongator(sizes[l + 1], 2) for l in range(nl - 1)]
+    pro = [prolongator(sizes[l + 1], 2, 2, args.boundary) for l in range(nl - 1)]
     starts = lanczos_starts(0, [s * s * b for s in sizes])
     bases = level_basis(p, nl)
     bvec = rhs(0, p.ndof)
@@ -149,20 +156,27 @@ def main():
     t0 = time.time()
     levels, info = build(from_problem(p), pro, bases, starts, tmax, args.workers)
     log(f"hierarchy built in {time.time() - t0:.0f} s")
-    out = {"workload": f"biharmonic-like 2D, {n}x{n} patches, b={b}, seed 0, {nl} levels, adaptive t_max={tmax}, "
-                       f"V({k},{k}) fourth-kind Chebyshev, PCG rtol 1e-8",
+    out = {"workload": f"biharmonic-like 2D, {n}x{n} patches, b={b}, seed 0, {nl} levels, bilinear transfer "
+                       f"({args.boundary} boundary), adaptive t_max={tmax}, V({k},{k}) fourth-kind Chebyshev, "
+                       f"PCG rtol 1e-8",
            "levels": info, "pcg": {}}
+    global _PCG
+    _PCG = (levels, starts, bvec, k)   # forked workers read it; only the form name is sent
     with ctx.Pool(3) as pool:
-        for form, rec, betas in pool.imap_unordered(
-                _pcg_worker, [(f, levels, starts, bvec, k) for f in ("fp64", "mixed_f32", "mixed_bf16g")]):
+        for form, rec, betas in pool.imap_unordered(_pcg_worker, ["fp64", "mixed_f32", "mixed_bf16g"]):
             if betas is not None:
                 rec["betas"] = betas
             out["pcg"][form] = rec
     path = (os.path.join(ROOT, "tests", "golden", "c1_pcg_iterations.json") if n == 512 and nl == 6
             else os.path.join(ROOT, "_work", f"golden_n{n}_l{nl}.json"))
     os.makedirs(os.path.dirname(path), exist_ok=True)
+    allrec = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            allrec = json.load(f)
+    allrec[args.boundary] = out
     with open(path, "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump(allrec, f, indent=1)
     log(f"wrote {path} ({time.time() - t0:.0f} s)")
 
 

@@ -29,26 +29,27 @@ def upload(p):
     return chf.bsr_create(p.nb, p.b, p.rowptr, p.colidx, p.vals)
 
 
-def hierarchy_inputs(n, dim, b, levels, seed):
-    """Prolongators (finest first) and Lanczos start vectors for each level."""
+def hierarchy_inputs(n, dim, b, levels, seed, order=2):
+    """Prolongators (finest first) and Lanczos start vectors for each level;
+    order: interpolation nodes per direction of the patch transfer."""
     sizes = grid_sizes(n, levels)
-    pro = [prolongator(sizes[l + 1], dim) for l in range(levels - 1)]
+    pro = [prolongator(sizes[l + 1], dim, order) for l in range(levels - 1)]
     starts = lanczos_starts(seed, [s ** dim * b for s in sizes])
     return pro, starts
 
 
-def oracle_levels(p, levels, mode="lower", tmax=0, seed=0, **kw):
+def oracle_levels(p, levels, mode="lower", tmax=0, seed=0, order=2, **kw):
     from oracle import solver
     from oracle.bsr import from_problem
-    pro, starts = hierarchy_inputs(p.n, p.dim, p.b, levels, seed)
+    pro, starts = hierarchy_inputs(p.n, p.dim, p.b, levels, seed, order)
     return solver.build_levels(from_problem(p), pro, starts, mode, tmax, bases=level_basis(p, levels), **kw)
 
 
-def gpu_levels(p, levels, degree, pattern, tmax=0, dtype=0, seed=0, betas=None, level0_pattern=None):
+def gpu_levels(p, levels, degree, pattern, tmax=0, dtype=0, seed=0, betas=None, level0_pattern=None, order=2):
     """Build the GPU hierarchy for problem p through the C ABI."""
     import paper_2509_06744_amd as chf
     A = upload(p)
-    pro, starts = hierarchy_inputs(p.n, p.dim, p.b, levels, seed)
+    pro, starts = hierarchy_inputs(p.n, p.dim, p.b, levels, seed, order)
     L = chf.levels_create(A)
     for ps, basis in zip(pro, level_basis(p, levels)):
         ps = ps.tocsr()

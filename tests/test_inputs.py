@@ -87,10 +87,52 @@ def test_seed_determinism():
 
 
 def test_prolongator_weights():
-    p1 = prolongator_1d(4).toarray()
+    p1 = prolongator_1d(4, boundary="zero_ghost").toarray()
     assert p1.shape == (8, 4)
     assert np.allclose(p1.sum(axis=1), [0.75, 1, 1, 1, 1, 1, 1, 0.75])
     assert p1[2, 1] == 0.75 and p1[2, 0] == 0.25 and p1[3, 2] == 0.25
+    d1 = prolongator_1d(4).toarray()
+    # Dirichlet-consistent linear interpolation differs only next to the
+    # boundary: t = -1/4 between the boundary point -3/4 (value 0) and cell 0
+    assert abs(d1[0, 0] - 2.0 / 3.0) < 1e-15 and abs(d1[7, 3] - 2.0 / 3.0) < 1e-15
+    assert np.array_equal(d1[1:7], p1[1:7])
     p2 = prolongator(4, 2)
     assert p2.shape == (64, 16)
-    assert np.allclose(p2.toarray(), np.kron(p1, p1))
+    assert np.allclose(p2.toarray(), np.kron(d1, d1))
+
+
+def _fine_coords(nc):
+    return np.array([i // 2 - 0.25 if i % 2 == 0 else i // 2 + 0.25 for i in range(2 * nc)])
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_prolongator_reproduces_polynomials(order):
+    # interior rows reproduce every polynomial of degree < order; rows next to
+    # a boundary reproduce those that vanish at the boundary point (-3/4 on
+    # the left, nc - 1/4 on the right), the Dirichlet condition of the grid
+    nc = 12
+    p = prolongator_1d(nc, order).toarray()
+    xc = np.arange(nc, dtype=float)
+    tf = _fine_coords(nc)
+    reach = order // 2 + 1          # fine rows within this many coarse cells see a boundary
+    inner = [f for f in range(2 * nc) if reach <= tf[f] <= nc - 1 - reach]
+    rng = np.random.default_rng(order)
+    for deg in range(order):
+        c = rng.standard_normal(deg + 1)
+        poly = np.polynomial.Polynomial(c)
+        assert np.allclose((p @ poly(xc))[inner], poly(tf)[inner], rtol=0, atol=1e-12 * np.abs(poly(tf)).max())
+    for deg in range(order - 1):
+        r = np.polynomial.Polynomial(rng.standard_normal(deg + 1))
+        for root, near in ((-0.75, tf < reach + 1), (nc - 0.25, tf > nc - 2 - reach)):
+            q = np.polynomial.Polynomial([-root, 1.0]) * r       # degree deg + 1 <= order - 1
+            got, want = p @ q(xc), q(tf)
+            assert np.allclose(got[near], want[near], rtol=0, atol=1e-11 * np.abs(want).max())
+    # a polynomial that does not vanish at the boundary is not reproduced there
+    ones = p @ np.ones(nc)
+    assert ones[0] < 1 - 1e-3 and ones[-1] < 1 - 1e-3
+
+
+def test_cubic_interior_weights():
+    p = prolongator_1d(8, 4).toarray() * 128
+    assert np.allclose(p[8, 2:6], [-5, 35, 105, -7])      # fine 2I, I = 4: cells I-2 .. I+1
+    assert np.allclose(p[9, 3:7], [-7, 105, 35, -5])      # fine 2I+1: cells I-1 .. I+2
