@@ -155,6 +155,22 @@ int chf_lmax_lanczos(chf_bsr A, chf_fsai G, chf_dtype dtype, int iters, const do
 int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree,
                      const void* b, void* x, int x_is_zero, void* work, hipStream_t stream);
 
+/* chf_cheb4_smooth without the work argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the call performs no allocation. Its
+ * three work vectors live in a library-owned device array of 64 MiB that
+ * every device the library runs on holds until the process ends, so
+ * 3 * N * sizeof(element) must not exceed 64 MiB (EINVAL otherwise: N up to
+ * 2,796,202 for CHF_F64, twice that for FP32 vectors). No part of the array
+ * needs to start at zero: each call writes every element it reads. Calls
+ * that overlap on one device (several streams or host threads) share the
+ * array and race; serialise them. For CHF_F32/CHF_BF16 the FP32 layout of A
+ * must already exist (one FP32 call of chf_cheb4_smooth or chf_bsr_spmv
+ * builds it), since building it allocates (EINVAL otherwise). Results are
+ * those of chf_cheb4_smooth with the same arguments. */
+int chf_cheb4_smooth_noalloc(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree,
+                             const void* b, void* x, int x_is_zero, hipStream_t stream);
+
 /* Comparators of Sec. 3.1, with the same arguments, layout and work buffer
  * as chf_cheb4_smooth:
  * - chf_cheb1_smooth: Algorithm 2 (Chebyshev iteration of the first kind)

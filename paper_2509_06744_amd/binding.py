@@ -13,7 +13,7 @@ __all__ = [
     "bsr_create", "bsr_export", "bsr_spmv",
     "pattern_lower", "pattern_from_csr", "pattern_adaptive", "pattern_export",
     "fsai_setup", "fsai_export", "fsai_apply", "bsr_triple", "fsai_nest", "lmax_lanczos",
-    "cheb4_smooth", "cheb1_smooth", "richardson_smooth",
+    "cheb4_smooth", "cheb4_smooth_noalloc", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
     "levels_set_beta", "levels_set_cycle", "levels_set_nesting", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
     "levels_energy_factor",
@@ -62,6 +62,7 @@ EXPORTED = {
     "chf_fsai_apply": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, _vp]),
     "chf_lmax_lanczos": (C.c_int, [_vp, _vp, C.c_int, C.c_int, _vp, _dbl, _pd, _pd, _vp]),
     "chf_cheb4_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
+    "chf_cheb4_smooth_noalloc": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp]),
     "chf_cheb1_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "chf_richardson_smooth": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.c_int, _vp, _vp, C.c_int, _vp, _vp]),
     "chf_levels_set_cycle": (C.c_int, [_vp, C.c_int, _dbl, C.c_int]),
@@ -311,6 +312,11 @@ def lmax_lanczos(A: Bsr, G: Fsai, v0, iters=100, safety=1.01, dtype=F64, stream=
 def cheb4_smooth(A: Bsr, G: Fsai, beta, degree, b, x, x_is_zero=False, work=None, dtype=F64, stream=None):
     _check(_fn("chf_cheb4_smooth")(A.h, G.h, dtype, float(beta), int(degree), _ptr(b), _ptr(x),
                                    int(bool(x_is_zero)), _ptr(work), _stream(stream)))
+
+
+def cheb4_smooth_noalloc(A: Bsr, G: Fsai, beta, degree, b, x, x_is_zero=False, dtype=F64, stream=None):
+    _check(_fn("chf_cheb4_smooth_noalloc")(A.h, G.h, int(dtype), float(beta), int(degree), _ptr(b), _ptr(x),
+                                           int(bool(x_is_zero)), _stream(stream)))
 
 
 def cheb1_smooth(A: Bsr, G: Fsai, alpha, beta, degree, b, x, x_is_zero=False, work=None, dtype=F64, stream=None):

@@ -11,9 +11,19 @@
 // With a nested factor (Sec. 2.2), M = G0^T G1^T G1 G0 and the middle of the
 // step becomes t = G0 r, t' = G1 t, t = G1^T t' (five kernels).
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
+
+// Work space of chf_cheb4_smooth_noalloc: the three vectors r, t, p of the
+// smoother step in one file-scope device array, so that the call allocates
+// nothing. Each device the library runs on holds its own copy until the
+// process ends. Host code must not pass `scratch` itself to a kernel (on the
+// host it is only a stand-in symbol): its device address comes from
+// hipGetSymbolAddress, taken once per device.
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
 
 namespace chf {
 
@@ -149,6 +159,49 @@ extern "C" int chf_cheb4_smooth(chf_bsr A, chf_fsai G, chf_dtype dtype, double b
                                 void* x, int x_is_zero, void* work, hipStream_t stream) {
     return with_operands(A, G, dtype, b, x, work, stream, [&](const Sell& sa, const FactorOps& g, chf_dtype vec) {
         cheb4_impl(sa, g, vec, beta, degree, b, x, x_is_zero != 0, work, stream);
+    });
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current, then cached).
+void* noalloc_scratch() {
+    int dev = 0;
+    CHF_HIP(hipGetDevice(&dev));
+    CHF_CHECK(dev >= 0 && dev < kMaxDevices, CHF_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        CHF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        CHF_CHECK(p != nullptr, CHF_EDEVICE, "no device address for the smoother scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int chf_cheb4_smooth_noalloc(chf_bsr A, chf_fsai G, chf_dtype dtype, double beta, int degree,
+                                        const void* b, void* x, int x_is_zero, hipStream_t stream) {
+    return guarded([&] {
+        CHF_CHECK(A && G && b && x, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(A->nb == G->nb && A->b == G->b, CHF_EINVAL, "A and G sizes differ");
+        CHF_CHECK(dtype == CHF_F64 || dtype == G->store, CHF_EINVAL,
+                  "dtype must be F64 or the factor's storage dtype");
+        const chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
+        const int64_t n = A->nb * (int64_t)A->b;
+        CHF_CHECK((size_t)n * 3 * vec_size(vec) <= kNoallocScratchBytes, CHF_EINVAL,
+                  "chf_cheb4_smooth_noalloc: 3 vectors of " + std::to_string(n) +
+                      " elements exceed its 64 MiB scratch");
+        // the FP32 layout of A is built on first use, which allocates
+        CHF_CHECK(vec == CHF_F64 || A->nb == 0 || A->sell32.nslices > 0, CHF_EINVAL,
+                  "chf_cheb4_smooth_noalloc: the FP32 layout of A does not exist yet (make one FP32 call of "
+                  "chf_cheb4_smooth or chf_bsr_spmv first)");
+        const Sell& sa = vec == CHF_F64 ? A->sell64 : A->sell32;
+        cheb4_impl(sa, factor_ops(*G, dtype), vec, beta, degree, b, x, x_is_zero != 0, noalloc_scratch(), stream);
     });
 }
 
