@@ -1,23 +1,30 @@
-"""Writes tests/golden/c1_pcg_iterations.json from the oracle alone.
+"""Writes the stored oracle results under tests/golden/ from the oracle alone.
 
-Workload: biharmonic-like 2D problem on 512 x 512 patches, b = 10, seed 0
-(A = R^T (L^2 (x) I_b) R), six-level Galerkin hierarchy with the bilinear
-patch transfer (--boundary dirichlet, the default: Lagrange interpolation
-with the Dirichlet boundary points as nodes; --boundary zero_ghost: the
-earlier reading with zero ghost cells), adaptive block-FSAI
-on every smoothed level (Algorithm 1, P0 = diagonal, tau = 1, t_max = 8),
-Lanczos bounds (Sec. 5: 100 steps, x 1.01), V(4,4) with fourth-kind Chebyshev
-smoothing, PCG from x = 0 to a recursive relative residual of 1e-8, in three
-forms: FP64 (Fletcher-Reeves), and the mixed forms with A, G in FP32 or A in
-FP32 and G in BF16 (flexible PCG around the FP32 cycle).
+--workload c1 (tests/golden/c1_pcg_iterations.json): biharmonic-like 2D
+problem on 512 x 512 patches, b = 10, seed 0 (A = R^T (L^2 (x) I_b) R),
+six-level Galerkin hierarchy with the bilinear patch transfer (--boundary
+dirichlet, the default: Lagrange interpolation with the Dirichlet boundary
+points as nodes; --boundary zero_ghost: the earlier reading with zero ghost
+cells), PCG to a recursive relative residual of 1e-8.
+
+--workload c2 (tests/golden/c2_n<N>_pcg_iterations.json): triharmonic-like
+2D problem (D = L^3) on N x N patches (default 32), b = 21, seed 0, three
+levels, cubic patch transfer with the Dirichlet boundary points as nodes,
+PCG to a recursive relative residual of 1e-10.
+
+Both: adaptive block-FSAI on every smoothed level (Algorithm 1, P0 =
+diagonal, tau = 1, t_max = 8), Lanczos bounds (Sec. 5: 100 steps, x 1.01),
+V(4,4) with fourth-kind Chebyshev smoothing, PCG from x = 0 in three forms:
+FP64 (Fletcher-Reeves), and the mixed forms with A, G in FP32 or A in FP32
+and G in BF16 (flexible PCG around the FP32 cycle).
 
 Only oracle/ and the input generator are called. Block rows are independent
 in Algorithm 1 and in the factor of Def. 2.2, so their rows are computed by a
 pool of worker processes, each running the oracle's own per-row functions on
 a contiguous chunk of rows; the results are the same as one serial pass.
-Run from the repository root:  python tests/golden/make_c1_golden.py
-(about an hour on 8 cores; --n 64 gives a quick smaller run written to
-_work/ instead of the golden file).
+Run from the repository root:  python tests/golden/make_golden.py
+(c1: about an hour on 8 cores; --n 64 gives a quick smaller c1 run written
+to _work/ instead of the golden file).
 """
 from __future__ import annotations
 
@@ -129,26 +136,31 @@ _PCG = None   # (levels, starts, bvec, k), shared with the forked PCG workers
 
 
 def _pcg_worker(form):
-    levels, starts, bvec, k = _PCG
+    levels, starts, bvec, k, rtol = _PCG
     if form == "fp64":
-        return form, run_pcg(form, levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, k), bvec, False), None
+        return form, run_pcg(form, levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, k), bvec, False,
+                             rtol), None
     ml = mixed.mixed_levels(levels, "f32" if form == "mixed_f32" else "bf16", starts)
     betas = [m.beta for m in ml[:-1]]
-    return form, run_pcg(form, levels[0].apply_a, mixed.precond_mixed(ml, k), bvec, True), betas
+    return form, run_pcg(form, levels[0].apply_a, mixed.precond_mixed(ml, k), bvec, True, rtol), betas
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--n", type=int, default=512)
-    ap.add_argument("--levels", type=int, default=6)
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2"])
+    ap.add_argument("--n", type=int, default=None)
+    ap.add_argument("--levels", type=int, default=None)
     ap.add_argument("--workers", type=int, default=max(1, min(8, os.cpu_count() or 1) - 1))
     ap.add_argument("--boundary", default="dirichlet", choices=["dirichlet", "zero_ghost"])
     args = ap.parse_args()
-    n, b, tmax, k = args.n, 10, 8, 4
-    nl = args.levels
-    p = make_problem(n, 2, b, 2, seed=0)
+    c1 = args.workload == "c1"
+    n = args.n or (512 if c1 else 32)
+    nl = args.levels or (6 if c1 else 3)
+    b, power, order, rtol = (10, 2, 2, 1e-8) if c1 else (21, 3, 4, 1e-10)
+    tmax, k = 8, 4
+    p = make_problem(n, 2, b, power, seed=0)
     sizes = grid_sizes(n, nl)
-    pro = [prolongator(sizes[l + 1], 2, 2, args.boundary) for l in range(nl - 1)]
+    pro = [prolongator(sizes[l + 1], 2, order, args.boundary) for l in range(nl - 1)]
     starts = lanczos_starts(0, [s * s * b for s in sizes])
     bases = level_basis(p, nl)
     bvec = rhs(0, p.ndof)
@@ -156,19 +168,22 @@ def main():
     t0 = time.time()
     levels, info = build(from_problem(p), pro, bases, starts, tmax, args.workers)
     log(f"hierarchy built in {time.time() - t0:.0f} s")
-    out = {"workload": f"biharmonic-like 2D, {n}x{n} patches, b={b}, seed 0, {nl} levels, bilinear transfer "
-                       f"({args.boundary} boundary), adaptive t_max={tmax}, V({k},{k}) fourth-kind Chebyshev, "
-                       f"PCG rtol 1e-8",
+    out = {"workload": f"{'biharmonic' if c1 else 'triharmonic'}-like 2D, {n}x{n} patches, b={b}, seed 0, "
+                       f"{nl} levels, {'bilinear' if order == 2 else 'cubic'} transfer ({args.boundary} boundary), "
+                       f"adaptive t_max={tmax}, V({k},{k}) fourth-kind Chebyshev, PCG rtol {rtol:g}",
            "levels": info, "pcg": {}}
     global _PCG
-    _PCG = (levels, starts, bvec, k)   # forked workers read it; only the form name is sent
+    _PCG = (levels, starts, bvec, k, rtol)   # forked workers read it; only the form name is sent
     with ctx.Pool(3) as pool:
         for form, rec, betas in pool.imap_unordered(_pcg_worker, ["fp64", "mixed_f32", "mixed_bf16g"]):
             if betas is not None:
                 rec["betas"] = betas
             out["pcg"][form] = rec
-    path = (os.path.join(ROOT, "tests", "golden", "c1_pcg_iterations.json") if n == 512 and nl == 6
-            else os.path.join(ROOT, "_work", f"golden_n{n}_l{nl}.json"))
+    if c1:
+        path = (os.path.join(ROOT, "tests", "golden", "c1_pcg_iterations.json") if n == 512 and nl == 6
+                else os.path.join(ROOT, "_work", f"golden_n{n}_l{nl}.json"))
+    else:
+        path = os.path.join(ROOT, "tests", "golden", f"c2_n{n}_pcg_iterations.json")
     os.makedirs(os.path.dirname(path), exist_ok=True)
     allrec = {}
     if os.path.exists(path):
