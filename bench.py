@@ -84,12 +84,14 @@ def parse():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--no-nested", action="store_true")
     ap.add_argument("--no-setup3d", action="store_true")
+    ap.add_argument("--no-c2", action="store_true", help="skip the mixed-precision triharmonic (b = 21) leg")
+    ap.add_argument("--only-c2", action="store_true", help="run only the triharmonic leg")
     ap.add_argument("--setup3d-grid", type=int, default=64, help="3D patch grid of the batched set-up leg")
     ap.add_argument("--setup3d-tmax", type=int, default=23)
     ap.add_argument("--only-setup3d", action="store_true",
                     help="run only the batched 3D set-up leg (for hardware-counter passes)")
     ap.add_argument("--train-seeds", type=int, default=32, help="training seeds 1..S")
-    ap.add_argument("--test-seeds", type=int, default=2, help="test seeds 100..100+T-1 (up to 8)")
+    ap.add_argument("--test-seeds", type=int, default=8, help="test seeds 100..100+T-1 (up to 8)")
     ap.add_argument("--cpu-grid", type=int, default=32, help="patches per side of the oracle's timing sample")
     ap.add_argument("--only-spmv", action="store_true",
                     help="build A only and run the level-0 residual SpMV (for hardware-counter passes)")
@@ -179,6 +181,111 @@ def setup3d_leg(args, chf, torch):
            "note": "fsai_setup_ms is the whole call: local factorisations, G^T transpose map, SpMV layouts"}
     log(f"3D batched set-up: {rec}")
     return rec
+
+
+def first_below(hist, tol):
+    """First iteration whose recursive relative residual is <= tol, or None."""
+    idx = np.nonzero(np.asarray(hist) <= tol)[0]
+    return int(idx[0]) if idx.size else None
+
+
+def c2_leg(args, chf, torch, dev):
+    """Mixed-precision triharmonic workload: D = L^3 (25-point block stencil),
+    256 x 256 patches, b = 21 (1,376,256 dofs), five Galerkin levels with the
+    cubic patch transfer, adaptive block-FSAI t_max = 8, V(4,4) fourth-kind
+    Chebyshev smoothing, outer FP64 PCG to a recursive relative residual of
+    1e-10. Forms: A and G in FP32, A in FP32 with G in BF16 (flexible PCG), and
+    the plain FP64 form for reference. For each: set-up and PCG time,
+    iterations, the recursive and the true residual, one level-0 smoother
+    application (median of 20 calls) against its algorithmic bytes, and that
+    application's error against the FP64 form's on the same inputs."""
+    from problems import CONFIGS, grid_sizes, lanczos_starts, level_basis, make_problem, prolongator, rhs
+    cfg = CONFIGS["c2"]
+    n, b, L, k = cfg.n, cfg.b, cfg.levels, cfg.degree
+    p = make_problem(n, 2, b, cfg.power, seed=cfg.seed)
+    sizes = grid_sizes(n, L)
+    pro = [prolongator(sizes[l + 1], 2, cfg.transfer_order) for l in range(L - 1)]
+    starts = lanczos_starts(cfg.seed, [s_ * s_ * b for s_ in sizes])
+    bases = level_basis(p, L)
+    bd = torch.from_numpy(rhs(cfg.seed, p.ndof)).to(dev)
+    A = chf.bsr_create(p.nb, p.b, p.rowptr, p.colidx, p.vals)
+    nnzb, N = p.nnzb, p.ndof
+    v0 = [torch.from_numpy(s_).to(dev) for s_ in starts[:-1]]
+    del p
+    stream = torch.cuda.current_stream()
+    out = {"workload": (f"triharmonic-like 2D PUM-shaped A=R^T(L^3 (x) I_b)R, {n}x{n} patches, b={b}, {N} dofs, "
+                        f"{L}-level Galerkin V({k},{k}), cubic patch transfer, adaptive t_max={cfg.tmax}, "
+                        f"PCG rtol {cfg.rtol:g}"), "nnzb_A": nnzb}
+    x64 = None
+    for name, dt in [("fp64", chf.F64), ("mixed_f32", chf.F32), ("mixed_bf16g", chf.BF16)]:
+        rec = {}
+        H = chf.levels_create(A)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for ps, basis in zip(pro, bases):
+            chf.levels_add_coarse(H, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
+        torch.cuda.synchronize()
+        rec["galerkin_ms"] = round(1e3 * (time.perf_counter() - t), 1)
+        t = time.perf_counter()
+        chf.levels_setup(H, degree=k, pattern=1, tmax=cfg.tmax, dtype=dt, v0=v0)
+        torch.cuda.synchronize()
+        rec["levels_setup_ms"] = round(1e3 * (time.perf_counter() - t), 1)
+        rec["blocks_per_row_A"] = []
+        for l in range(L):
+            Al, _, _ = chf.levels_get(H, l)
+            nb_l, _, nz_l = Al.info()
+            rec["blocks_per_row_A"].append(round(nz_l / nb_l, 1))
+        flex = dt != chf.F64
+        xs = torch.zeros(N, dtype=torch.float64, device=dev)
+        chf.pcg_solve(H, bd, xs, rtol=cfg.rtol, maxit=400, flexible=flex, raise_on_noconv=False)   # warm-up
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it, hist, tr, rc = chf.pcg_solve(H, bd, xs, rtol=cfg.rtol, maxit=400, flexible=flex, raise_on_noconv=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        rec.update({"iterations": it, "time_ms": round(1e3 * el, 2), "ms_per_iteration": round(1e3 * el / max(it, 1), 3),
+                    "final_relres": float(hist[-1]), "true_relres": tr, "converged": rc == 0, "flexible_cg": flex,
+                    "iterations_to": {f"{t:g}": first_below(hist, t) for t in (1e-6, 1e-8, 1e-10)}})
+        # one level-0 smoother application with this form's operators, x0 = 0
+        A0, G0, P0 = chf.levels_get(H, 0)
+        beta0 = chf.levels_get_beta(H, 0)
+        _, pcol = chf.pattern_export(P0)
+        nnzg = len(pcol)
+        vt = torch.float64 if dt == chf.F64 else torch.float32
+        bb_ = bd.to(vt)
+        x = torch.zeros(N, dtype=vt, device=dev)
+        work = torch.zeros(3 * N, dtype=vt, device=dev)
+        for _ in range(3):
+            chf.cheb4_smooth(A0, G0, beta0, k, bb_, x, x_is_zero=False, work=work, dtype=dt)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+        for a_, b_ in evs:
+            a_.record(stream)
+            chf.cheb4_smooth(A0, G0, beta0, k, bb_, x, x_is_zero=False, work=work, dtype=dt)
+            b_.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
+        sa, sv = (8, 8) if dt == chf.F64 else (4, 4)
+        sg = 8 if dt == chf.F64 else (4 if dt == chf.F32 else 2)
+        b_app = k * (nnzb * (b * b * sa + 4) + 2 * nnzg * (b * b * sg + 4) + 10 * N * sv)
+        rec["smoother"] = {"median_ms_per_application_20_calls": round(ms, 4), "algorithmic_bytes_per_application": b_app,
+                           "achieved_GBs": round(b_app / (ms * 1e-3) / 1e9, 1),
+                           "hbm_frac": round(b_app / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "gdofs": round(N * k / (ms * 1e-3) / 1e9, 4), "nnzb_G": nnzg}
+        # error of one application from x0 = 0 against the FP64 form's
+        x.zero_()
+        chf.cheb4_smooth(A0, G0, beta0, k, bb_, x, x_is_zero=True, work=work, dtype=dt)
+        xd = x.double()
+        if x64 is None:
+            x64 = xd.clone()
+        else:
+            rec["smoother"]["rel_error_vs_fp64_application"] = float((xd - x64).abs().max() / x64.abs().max())
+        out[name] = rec
+        log(f"c2 {name}: {rec}")
+        H.destroy()
+        del work, x
+    out["mixed_f32_over_fp64_time"] = round(out["mixed_f32"]["time_ms"] / out["fp64"]["time_ms"], 4)
+    out["mixed_bf16g_over_fp64_time"] = round(out["mixed_bf16g"]["time_ms"] / out["fp64"]["time_ms"], 4)
+    return out
 
 
 def comparators_leg(args, chf, torch, dev, H, A, bd, N, k):
@@ -286,14 +393,19 @@ def nested_leg(args, chf, torch, dev, A, bd, N, k, pro, bases, v0, H_plain, plai
 
 def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
     """Train the pattern proposer on Algorithm 1's patterns (seeds 1..S of the
-    2D 64x64 and 3D 12^3 generators, b = 10, t_max = 8), then compare it with
-    Algorithm 1 on the benchmark grid for seeds 100.. : time to form the
-    level-0 pattern, and the V(k,k) energy-norm convergence factor with that
-    pattern (coarser levels use Algorithm 1 in both cases)."""
+    2D 64x64 and 3D 12^3 generators, b = 10, t_max = 8), then compare three
+    level-0 patterns on the benchmark grid for seeds 100..107: Algorithm 1,
+    the network's proposal, and the interior template (the offsets of
+    Algorithm 1's pattern at the centre row of a 64x64 training grid, applied
+    at every row). For each: the time to form the pattern, the share of rows
+    identical to Algorithm 1's, and the V(k,k) energy-norm convergence factor
+    with that pattern on level 0 (coarser levels use Algorithm 1 in every
+    case)."""
     from paper_2509_06744_amd import learned
     from problems import lanczos_starts, level_basis, make_problem, mlp_init, permutation, uniform_start
     t0 = time.perf_counter()
     items, keep = [], []
+    tmpl = None
     for seed in range(1, args.train_seeds + 1):
         for nn, dim in [(64, 2), (12, 3)]:
             q = make_problem(nn, dim, b, 2, seed=seed)
@@ -301,6 +413,9 @@ def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
             Pq = chf.pattern_adaptive(Aq, args.tmax)
             items.append((Aq, nn, nn, Pq))
             keep.append((Aq, Pq))
+            if tmpl is None and dim == 2:
+                rp_, cp_ = chf.pattern_export(Pq)
+                tmpl = learned.template_offsets(rp_, cp_, nn, nn, (nn // 2) * nn + nn // 2)
     X, Y = learned.dataset(items)
     t_data = time.perf_counter() - t0
     torch.cuda.synchronize()
@@ -319,18 +434,26 @@ def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
         e0 = torch.from_numpy(uniform_start(seed, q.ndof)).to(dev)
         qb = level_basis(q, L)
         rec = {"seed": seed}
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        Pa = chf.pattern_adaptive(Aq, args.tmax)
-        rec["pattern_ms_adaptive"] = round(1e3 * (time.perf_counter() - t), 2)
-        t = time.perf_counter()
-        Pl = chf.mlp_propose(Aq, net, n, n, args.tmax)
-        rec["pattern_ms_learned"] = round(1e3 * (time.perf_counter() - t), 2)
-        ra, ca = chf.pattern_export(Pa)
-        rl, cl = chf.pattern_export(Pl)
-        same = sum(1 for kk in range(q.nb) if np.array_equal(ca[ra[kk]:ra[kk + 1]], cl[rl[kk]:rl[kk + 1]]))
-        rec["rows_identical"] = round(same / q.nb, 4)
-        for name, P in [("adaptive", Pa), ("learned", Pl)]:
+        pats = {}
+        for name, make in [("adaptive", lambda: chf.pattern_adaptive(Aq, args.tmax)),
+                           ("learned", lambda: chf.mlp_propose(Aq, net, n, n, args.tmax)),
+                           ("template", lambda: chf.pattern_template(n, n, 1, tmpl))]:
+            best = None
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                P = make()
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t
+                best = el if best is None else min(best, el)
+            pats[name] = P
+            rec[f"pattern_ms_{name}"] = round(1e3 * best, 2)
+        ra, ca = chf.pattern_export(pats["adaptive"])
+        for name in ("learned", "template"):
+            rl, cl = chf.pattern_export(pats[name])
+            same = sum(1 for kk in range(q.nb) if np.array_equal(ca[ra[kk]:ra[kk + 1]], cl[rl[kk]:rl[kk + 1]]))
+            rec[f"rows_identical_{name}"] = round(same / q.nb, 4)
+        for name, P in pats.items():
             H = chf.levels_create(Aq)
             for ps, basis in zip(pro, qb):
                 chf.levels_add_coarse(H, ps.shape[1], ps.indptr, ps.indices, ps.data, basis)
@@ -344,12 +467,19 @@ def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
             rec[f"cycles_{name}"] = cyc
             H.destroy()
         tests.append(rec)
-        log(f"learned vs adaptive: {rec}")
+        log(f"learned vs adaptive vs template: {rec}")
         del q
+    summ = {}
+    for name in ("adaptive", "learned", "template"):
+        summ[f"pattern_ms_{name}_mean"] = round(float(np.mean([t[f"pattern_ms_{name}"] for t in tests])), 2)
+        summ[f"rho_A_{name}_mean"] = round(float(np.mean([t[f"rho_A_{name}"] for t in tests])), 5)
+    for name in ("learned", "template"):
+        summ[f"rows_identical_{name}_mean"] = round(float(np.mean([t[f"rows_identical_{name}"] for t in tests])), 4)
     return {"train": {"seeds": f"1..{args.train_seeds}", "grids": "64x64 2D and 12^3 3D, b=10, t_max=8",
                       "samples": int(len(perm)), "epochs": 4, "loss": [round(float(v), 5) for v in hist],
                       "data_s": round(t_data, 2), "train_s": round(t_train, 2)},
-            "test": tests}
+            "template_offsets": [list(map(int, o)) for o in tmpl],
+            "test": tests, "summary": summ}
 
 
 def main():
@@ -366,6 +496,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.only_setup3d:
         print(json.dumps({"setup3d": setup3d_leg(args, chf, torch)}), flush=True)
+        return
+    if args.only_c2:
+        print(json.dumps({"c2": c2_leg(args, chf, torch, dev)}), flush=True)
         return
     if args.calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
@@ -609,6 +742,8 @@ def main():
         out["learned"] = learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases)
     if not args.no_setup3d:
         out["setup3d"] = setup3d_leg(args, chf, torch)
+    if not args.no_c2:
+        out["c2"] = c2_leg(args, chf, torch, dev)
 
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")

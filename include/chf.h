@@ -102,6 +102,15 @@ int chf_pattern_from_csr(int64_t nb, const int64_t* rowptr, const int32_t* colid
  * P0 plus tmax must not exceed 32 blocks (EINVAL). ENOTSPD if a local matrix
  * is not positive definite. tmax = 0 returns a copy of P0. */
 int chf_pattern_adaptive(chf_bsr A, chf_pattern P0, int tmax, double tau, chf_pattern* out);
+/* Pattern from a stencil template on an nx x ny x nz patch grid (block
+ * index i = ix + nx (iy + ny iz)): row k holds k and every k + (dx, dy, dz)
+ * of the noff offsets (host int32[noff][3]) that stays inside the grid. Each
+ * offset must point to a smaller index (dx + nx (dy + ny dz) < 0, EINVAL
+ * otherwise). Not part of the paper: with a template read off Algorithm 1's
+ * pattern of an interior row, it is the translation-invariant baseline that
+ * the learned proposer is compared with. */
+int chf_pattern_template(int64_t nx, int64_t ny, int64_t nz, int32_t noff, const int32_t* offsets,
+                         chf_pattern* out);
 int chf_pattern_info(chf_pattern P, int64_t* nb, int64_t* nnz);
 int chf_pattern_export(chf_pattern P, int64_t* rowptr, int32_t* colidx);
 int chf_pattern_destroy(chf_pattern P);
@@ -276,14 +285,14 @@ int chf_bicgstab_solve(chf_levels L, const double* b, double* x, double rtol, in
  * the reference it is judged against. */
 /* Candidate features for the learned pattern proposer: for each block row k
  * and each candidate c in the strictly lower part of the row pattern of A^2,
- * 4 FP32 features: ||A_kc||_F, ||A_cc^{-1} A_ck||_F, patch distance |k - c|
+ * 6 FP32 features: ||A_kc||_F, ||A_cc^{-1} A_ck||_F, the signed patch offset (dx, dy, dz) of c from k
  * measured on the grid given by (nx, ny) (nz implied), and the one-step gain
  * -log rho_c at P = {k} (Lemma 2.4). Features are written to a device buffer
  * (float[ncand*4]); the candidate CSR (host int64 rowptr[nb+1], int32
  * cols[ncand]) is returned through chf_mlp_candidates. */
 int chf_mlp_candidates(chf_bsr A, int64_t* ncand, int64_t* rowptr, int32_t* cols);
 int chf_mlp_features(chf_bsr A, int32_t nx, int32_t ny, float* feats, hipStream_t stream);
-/* 4 -> 64 -> 64 -> 1 MLP with ReLU, FP32 parameters (4545 floats, layout
+/* 6 -> 64 -> 64 -> 1 MLP with ReLU, FP32 parameters (4673 floats, layout
  * W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3) and Adam moments. */
 int chf_mlp_create(const float* params_host, chf_mlp* out);
 int chf_mlp_destroy(chf_mlp net);
@@ -291,7 +300,7 @@ int chf_mlp_get_params(chf_mlp net, float* params_host);
 /* Logits for n feature rows (device float[n*4] -> float[n]). */
 int chf_mlp_forward(chf_mlp net, const float* feats, int64_t n, float* logits, hipStream_t stream);
 /* Mean binary cross-entropy-with-logits loss and its gradient (device
- * float[4545] written to grad) over n rows with labels in {0, 1}. */
+ * float[4673] written to grad) over n rows with labels in {0, 1}. */
 int chf_mlp_loss_grad(chf_mlp net, const float* feats, const float* labels, int64_t n,
                       float* loss_host, float* grad, hipStream_t stream);
 /* One Adam step (lr, beta1, beta2, eps) on the mini-batch. */

@@ -5,10 +5,10 @@ Features of candidate c for block row k (c in the strictly lower part of the
 row pattern of A^2):
   f0 = ||A_kc||_F / sqrt(||A_kk||_F ||A_cc||_F)
   f1 = ||A_cc^{-1} A_ck||_F
-  f2 = Euclidean distance between the patch centres
-  f3 = one-step gain -log rho_c with P_k = {k} (Lemma 2.4)
+  f2, f3, f4 = signed patch offset (dx, dy, dz) of c from k on the grid
+  f5 = one-step gain -log rho_c with P_k = {k} (Lemma 2.4)
 Label: c belongs to the final pattern of Algorithm 1. Loss: mean binary
-cross-entropy with logits. Parameter layout (4545 values): W1[64][4], b1[64],
+cross-entropy with logits. Parameter layout (4673 values): W1[64][6], b1[64],
 W2[64][64], b2[64], W3[64], b3.
 """
 from __future__ import annotations
@@ -18,17 +18,23 @@ import numpy as np
 from . import adaptive
 from .bsr import Bsr
 
-H, NIN, NPARAM = 64, 4, 4545
+H, NIN = 64, 6
+NPARAM = H * NIN + H + H * H + H + H + 1
 
 
 def unpack(p):
     p = np.asarray(p, dtype=np.float64)
-    w1 = p[0:256].reshape(64, 4)
-    b1 = p[256:320]
-    w2 = p[320:4416].reshape(64, 64)
-    b2 = p[4416:4480]
-    w3 = p[4480:4544]
-    b3 = p[4544]
+    o = 0
+    w1 = p[o:o + H * NIN].reshape(H, NIN)
+    o += H * NIN
+    b1 = p[o:o + H]
+    o += H
+    w2 = p[o:o + H * H].reshape(H, H)
+    o += H * H
+    b2 = p[o:o + H]
+    o += H
+    w3 = p[o:o + H]
+    b3 = p[o + H]
     return w1, b1, w2, b2, w3, b3
 
 
@@ -94,9 +100,9 @@ def features(a: Bsr, nx: int, ny: int, rows=None):
             cx, cy, cz = c % nx, (c // nx) % ny, c // (nx * ny)
             f.append([np.linalg.norm(akc) / np.sqrt(np.linalg.norm(akk) * np.linalg.norm(acc)),
                       np.linalg.norm(np.linalg.solve(acc, akc.T)),
-                      np.sqrt((cx - kx) ** 2 + (cy - ky) ** 2 + (cz - kz) ** 2),
+                      cx - kx, cy - ky, cz - kz,
                       gc])
-        out[int(k)] = (np.array(cand, dtype=np.int64), np.array(f).reshape(-1, 4))
+        out[int(k)] = (np.array(cand, dtype=np.int64), np.array(f).reshape(-1, NIN))
     return crow, ccol, out
 
 

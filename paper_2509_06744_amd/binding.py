@@ -7,11 +7,11 @@ import os
 import numpy as np
 
 __all__ = [
-    "F64", "F32", "BF16", "SMOOTH_CHEB4", "SMOOTH_CHEB1", "SMOOTH_RICHARDSON", "CYCLE_VKK", "CYCLE_V2K0",
+    "F64", "F32", "BF16", "NFEAT", "NPARAM", "SMOOTH_CHEB4", "SMOOTH_CHEB1", "SMOOTH_RICHARDSON", "CYCLE_VKK", "CYCLE_V2K0",
     "ChfError", "lib", "lib_path", "version", "current_stream",
     "Bsr", "Pattern", "Fsai", "Levels", "Mlp", "LevelOpts",
     "bsr_create", "bsr_export", "bsr_spmv",
-    "pattern_lower", "pattern_from_csr", "pattern_adaptive", "pattern_export",
+    "pattern_lower", "pattern_from_csr", "pattern_adaptive", "pattern_template", "pattern_export",
     "fsai_setup", "fsai_export", "fsai_apply", "bsr_triple", "fsai_nest", "lmax_lanczos",
     "cheb4_smooth", "cheb4_smooth_noalloc", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
@@ -27,6 +27,7 @@ F64, F32, BF16 = 0, 1, 2
 SMOOTH_CHEB4, SMOOTH_CHEB1, SMOOTH_RICHARDSON = 0, 1, 2
 CYCLE_VKK, CYCLE_V2K0 = 0, 1
 CHF_ENOCONV = -5
+NFEAT, NPARAM = 6, 4673   # learned proposer: features per candidate, network parameters
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(HERE, "libchf.so")
@@ -53,6 +54,7 @@ EXPORTED = {
     "chf_pattern_lower": (C.c_int, [_vp, C.POINTER(_vp)]),
     "chf_pattern_from_csr": (C.c_int, [_i64, _vp, _vp, C.POINTER(_vp)]),
     "chf_pattern_adaptive": (C.c_int, [_vp, _vp, C.c_int, _dbl, C.POINTER(_vp)]),
+    "chf_pattern_template": (C.c_int, [_i64, _i64, _i64, _i32, _vp, C.POINTER(_vp)]),
     "chf_pattern_info": (C.c_int, [_vp, _pi64, _pi64]),
     "chf_pattern_export": (C.c_int, [_vp, _vp, _vp]),
     "chf_pattern_destroy": (C.c_int, [_vp]),
@@ -251,6 +253,15 @@ def pattern_from_csr(nb, rowptr, colidx) -> Pattern:
 def pattern_adaptive(A: Bsr, tmax: int, tau: float = 1.0, p0: Pattern | None = None) -> Pattern:
     out = C.c_void_p()
     _check(_fn("chf_pattern_adaptive")(A.h, p0.h if p0 is not None else None, int(tmax), float(tau),
+                                       C.byref(out)))
+    return Pattern(out)
+
+
+def pattern_template(nx, ny, nz, offsets) -> Pattern:
+    """offsets: int array [noff, 3] of (dx, dy, dz), each to a smaller index."""
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32).reshape(-1, 3))
+    out = C.c_void_p()
+    _check(_fn("chf_pattern_template")(int(nx), int(ny), int(nz), off.shape[0], off.ctypes.data_as(C.c_void_p),
                                        C.byref(out)))
     return Pattern(out)
 
@@ -462,7 +473,7 @@ def mlp_create(params) -> Mlp:
 
 
 def mlp_get_params(net: Mlp):
-    out = np.empty(4545, np.float32)
+    out = np.empty(NPARAM, np.float32)
     _check(_fn("chf_mlp_get_params")(net.h, out.ctypes.data_as(C.c_void_p)))
     return out
 

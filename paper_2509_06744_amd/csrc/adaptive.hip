@@ -1104,9 +1104,9 @@ extern "C" int chf_pattern_adaptive(chf_bsr A, chf_pattern P0, int tmax, double 
 
 // ------------------------------------------------ learned-pattern features --
 // For block row k and each candidate c of the strictly lower part of the row
-// pattern of A^2, four features: ||A_kc||_F / sqrt(||A_kk||_F ||A_cc||_F),
-// ||A_cc^{-1} A_ck||_F, the Euclidean distance of the patch centres, and the
-// one-step gain -log rho_c at P_k = {k} (Lemma 2.4 with P~ empty:
+// pattern of A^2, six features: ||A_kc||_F / sqrt(||A_kk||_F ||A_cc||_F),
+// ||A_cc^{-1} A_ck||_F, the signed patch offset (dx, dy, dz) of c from k on
+// the grid, and the one-step gain -log rho_c at P_k = {k} (Lemma 2.4 with P~ empty:
 // H_kk = A_kk, H_kc = A_kc, W_c = A_cc). The gain uses the same batch code as
 // Algorithm 1.
 namespace chf {
@@ -1191,11 +1191,13 @@ __global__ __launch_bounds__(64) void k_mlp_features(int64_t nb, int b, int nx, 
                 const int c = cand[s0 + ci];
                 const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
                 const double dx = cx - kx, dy = cy - ky, dz = cz - kz;
-                float* f = feats + (c0 + s0 + ci) * 4;
+                float* f = feats + (c0 + s0 + ci) * MLP_NIN;
                 f[0] = (float)(sqrt(fkc) / sqrt(nkk * sqrt(fcc)));
                 f[1] = (float)sqrt(fv);
-                f[2] = (float)sqrt(dx * dx + dy * dy + dz * dz);
-                f[3] = (float)gain[s0 + ci];
+                f[2] = (float)dx;
+                f[3] = (float)dy;
+                f[4] = (float)dz;
+                f[5] = (float)gain[s0 + ci];
             }
             __syncthreads();
         }

@@ -52,60 +52,79 @@ SellPlan sell_plan(int64_t nb, int b, const std::vector<int64_t>& rowptr,
     return p;
 }
 
+// Column runs of one slot row: run q covers columns start[q] .. start[q+1]-1.
+struct SellRuns {
+    int n = 0;
+    int start[65] = {};
+};
+
+// Run widths of the layouts with a specialised SpMV (16-byte loads where the
+// block width allows):
+//   b = 10: FP64 2 x 5; FP32 4, 4, 2; BF16 8, 2;
+//   b = 21: FP64 2 x 10, 1; FP32 4 x 5, 1; BF16 8, 8, 4, 1;
+// every other b: single columns. The id V is the widest run.
+static SellRuns sell_runs(int b, chf_dtype t, int* V) {
+    std::vector<int> w;
+    if (b == 10) {
+        if (t == CHF_F64) w = {2, 2, 2, 2, 2};
+        else if (t == CHF_F32) w = {4, 4, 2};
+        else w = {8, 2};
+    } else if (b == 21) {
+        if (t == CHF_F64) w = {2, 2, 2, 2, 2, 2, 2, 2, 2, 2, 1};
+        else if (t == CHF_F32) w = {4, 4, 4, 4, 4, 1};
+        else w = {8, 8, 4, 1};
+    } else {
+        w.assign(b, 1);
+    }
+    SellRuns r;
+    r.n = (int)w.size();
+    int v = 1;
+    for (int q = 0; q < r.n; ++q) {
+        r.start[q + 1] = r.start[q] + w[q];
+        v = std::max(v, w[q]);
+    }
+    if (V) *V = v;
+    return r;
+}
+
+// Elements per slot: b * L, padded to a multiple of 16 bytes when runs are
+// loaded 16 bytes at a time (keeps every run of every slot aligned).
+__host__ __device__ constexpr int sell_slot_stride(int b, int L, int V, int elem) {
+    return V == 1 ? b * L : (b * L * elem + 15) / 16 * 16 / elem;
+}
+
 template <typename T>
-__global__ void k_sell_pack(int64_t total, int b, int S, int L, int V, const int64_t* __restrict__ src,
-                            const double* __restrict__ blocks, int transpose, T* __restrict__ out) {
-    const int64_t bl = (int64_t)b * L;
-    const int LV = L * V;
+__global__ void k_sell_pack(int64_t total, int b, int S, int L, int stride, SellRuns runs,
+                            const int64_t* __restrict__ src, const double* __restrict__ blocks, int transpose,
+                            T* __restrict__ out) {
+    const int bl = b * L;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
          e += (int64_t)gridDim.x * blockDim.x) {
-        int64_t slot = e / bl;
-        int rem = (int)(e - slot * bl);
-        int lane, c;
-        if (V == 8) {
-            // b = 10, BF16: runs of 8 and 2 columns (L * 8, L * 2 values)
-            if (rem < 8 * L) {
-                lane = rem / 8;
-                c = rem - lane * 8;
-            } else {
-                const int rem2 = rem - 8 * L;
-                lane = rem2 / 2;
-                c = 8 + (rem2 - lane * 2);
-            }
-        } else if (V == 4) {
-            // b = 10: runs of 4, 4 and 2 columns (L * 4, L * 4, L * 2 values)
-            if (rem < 8 * L) {
-                const int q = rem / (4 * L), rem2 = rem - q * 4 * L;
-                lane = rem2 / 4;
-                c = q * 4 + (rem2 - lane * 4);
-            } else {
-                const int rem2 = rem - 8 * L;
-                lane = rem2 / 2;
-                c = 8 + (rem2 - lane * 2);
-            }
-        } else {
-            const int q = rem / LV;
-            const int rem2 = rem - q * LV;
-            lane = rem2 / V;
-            c = q * V + (rem2 - lane * V);
-        }
-        int lr = lane / b, r = lane - lr * b;
-        int64_t sb = src[slot * S + lr];
+        const int64_t slot = e / stride;
+        const int rem = (int)(e - slot * stride);
         double v = 0.0;
-        if (sb >= 0) {
-            const double* blk = blocks + sb * b * b;
-            v = transpose ? blk[c * b + r] : blk[r * b + c];
+        if (rem < bl) {
+            int q = 0;
+            while (q + 1 < runs.n && L * runs.start[q + 1] <= rem) ++q;
+            const int w = runs.start[q + 1] - runs.start[q];
+            const int rem2 = rem - L * runs.start[q];
+            const int lane = rem2 / w;
+            const int c = runs.start[q] + (rem2 - lane * w);
+            const int lr = lane / b, r = lane - lr * b;
+            const int64_t sb = src[slot * S + lr];
+            if (sb >= 0) {
+                const double* blk = blocks + sb * b * b;
+                v = transpose ? blk[c * b + r] : blk[r * b + c];
+            }
         }
         store_from_f64<T>(out + e, v);
     }
 }
 
-// Lane vector width of the layout for the block sizes with a specialised
-// SpMV: b = 10 stores pairs of columns for FP64 (16-byte loads), runs of 4, 4
-// and 2 columns for FP32 (16- and 8-byte loads, marked V = 4) and runs of 8
-// and 2 columns for BF16 (16- and 4-byte loads, marked V = 8).
 static int sell_vec_width(int b, chf_dtype t) {
-    return b == 10 ? (t == CHF_F64 ? 2 : t == CHF_F32 ? 4 : 8) : 1;
+    int v = 1;
+    sell_runs(b, t, &v);
+    return v;
 }
 
 void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, bool transpose,
@@ -114,7 +133,8 @@ void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, boo
     out.b = plan.b;
     out.S = plan.S;
     out.L = plan.L;
-    out.V = sell_vec_width(plan.b, dtype);
+    const SellRuns runs = sell_runs(plan.b, dtype, &out.V);
+    out.stride = sell_slot_stride(plan.b, plan.L, out.V, (int)dtype_size(dtype));
     out.nslices = plan.nslices;
     out.nslots = plan.nslots;
     out.dtype = dtype;
@@ -124,19 +144,19 @@ void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, boo
     out.cols.upload(plan.cols.data(), plan.cols.size(), s);
     DevBuf<int64_t> src(std::max<size_t>(1, plan.src.size()));
     src.upload(plan.src.data(), plan.src.size(), s);
-    int64_t total = plan.nslots * plan.b * plan.L;
+    int64_t total = plan.nslots * (int64_t)out.stride;
     out.vals.alloc(std::max<int64_t>(1, total) * dtype_size(dtype));
     if (total > 0) {
         int grid = (int)std::min<int64_t>((total + 255) / 256, 65536);
         if (dtype == CHF_F64)
             hipLaunchKernelGGL((k_sell_pack<double>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
-                               out.V, src.p, d_src_blocks, (int)transpose, (double*)out.vals.p);
+                               out.stride, runs, src.p, d_src_blocks, (int)transpose, (double*)out.vals.p);
         else if (dtype == CHF_F32)
             hipLaunchKernelGGL((k_sell_pack<float>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
-                               out.V, src.p, d_src_blocks, (int)transpose, (float*)out.vals.p);
+                               out.stride, runs, src.p, d_src_blocks, (int)transpose, (float*)out.vals.p);
         else
             hipLaunchKernelGGL((k_sell_pack<bf16_t>), dim3(grid), dim3(256), 0, s, total, plan.b, plan.S, plan.L,
-                               out.V, src.p, d_src_blocks, (int)transpose, (bf16_t*)out.vals.p);
+                               out.stride, runs, src.p, d_src_blocks, (int)transpose, (bf16_t*)out.vals.p);
         CHF_LAUNCH_CHECK();
     }
     // src is freed at scope exit; make sure the pack has consumed it.
@@ -298,6 +318,48 @@ __device__ inline TV sell_lane_sum(int b, int S, int L, int lane, int lr, int j_
             acc += Pair<4, TA, TV, NTL>::dot(v + 4 * L + lane * 4, xc + 4);
             acc += Pair<2, TA, TV, NTL>::dot(v + 8 * L + lane * 2, xc + 8);
             v += STEP * stride;
+            cp += STEP * S;
+        }
+    } else if constexpr (BT == 21) {
+        // FP64: ten runs of 2 and one of 1 column; FP32: five runs of 4 and
+        // one of 1; BF16: runs of 8, 8, 4 and 1 (16-byte loads but for the
+        // last column); slots padded to 16 bytes
+        constexpr int SS = sell_slot_stride(21, 63, V, (int)sizeof(TA));
+        const TA* v = vals + (int64_t)j_first * SS;
+        const int* cp = cols + (int64_t)j_first * S + lr;
+#pragma unroll 1
+        for (int j = j_first; j < j1; j += STEP) {
+            // x + 21 col is only 8- (FP64) or 4-byte (FP32) aligned: x is read
+            // one value at a time, the matrix runs 16 bytes at a time
+            const TV* xc = x + (int64_t)(*cp) * 21;
+            if constexpr (sizeof(TA) == 8) {
+#pragma unroll
+                for (int q = 0; q < 10; ++q) {
+                    d2v a;
+                    if constexpr (NTL)
+                        a = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(v + q * 2 * L + lane * 2));
+                    else
+                        a = *reinterpret_cast<const d2v*>(v + q * 2 * L + lane * 2);
+                    acc += (TV)a.x * xc[2 * q] + (TV)a.y * xc[2 * q + 1];
+                }
+            } else if constexpr (sizeof(TA) == 4) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    f4v a;
+                    if constexpr (NTL)
+                        a = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(v + q * 4 * L + lane * 4));
+                    else
+                        a = *reinterpret_cast<const f4v*>(v + q * 4 * L + lane * 4);
+                    acc += ((TV)a.x * xc[4 * q] + (TV)a.y * xc[4 * q + 1]) +
+                           ((TV)a.z * xc[4 * q + 2] + (TV)a.w * xc[4 * q + 3]);
+                }
+            } else {
+                acc += Pair<8, TA, TV, NTL>::dot(v + lane * 8, xc);
+                acc += Pair<8, TA, TV, NTL>::dot(v + 8 * L + lane * 8, xc + 8);
+                acc += Pair<4, TA, TV, NTL>::dot(v + 16 * L + lane * 4, xc + 16);
+            }
+            acc += Pair<1, TA, TV, NTL>::dot(v + 20 * L + lane, xc + 20);
+            v += STEP * SS;
             cp += STEP * S;
         }
     } else if constexpr (BT > 0) {
@@ -464,7 +526,14 @@ static void launch_spmv_b(const Sell& A, const void* x, void* y, const void* bv,
             else
                 launch_spmv_t<10, 8, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
             break;
-        case 21: launch_spmv_t<21, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
+        case 21:
+            if constexpr (sizeof(TA) == 8)
+                launch_spmv_t<21, 2, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
+            else if constexpr (sizeof(TA) == 4)
+                launch_spmv_t<21, 4, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
+            else
+                launch_spmv_t<21, 8, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s);
+            break;
         default: launch_spmv_t<0, 1, TA, TV>(A, x, y, bv, epi, p, xo, alpha, beta, s); break;
     }
 }

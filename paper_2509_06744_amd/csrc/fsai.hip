@@ -917,6 +917,40 @@ extern "C" int chf_pattern_from_csr(int64_t nb, const int64_t* rowptr, const int
     });
 }
 
+extern "C" int chf_pattern_template(int64_t nx, int64_t ny, int64_t nz, int32_t noff, const int32_t* offsets,
+                                    chf_pattern* out) {
+    return guarded([&] {
+        CHF_CHECK(out && nx >= 1 && ny >= 1 && nz >= 1 && noff >= 0 && (noff == 0 || offsets), CHF_EINVAL,
+                  "bad argument");
+        std::vector<int64_t> lin(noff);
+        for (int32_t t = 0; t < noff; ++t) {
+            const int64_t dx = offsets[3 * t], dy = offsets[3 * t + 1], dz = offsets[3 * t + 2];
+            lin[t] = dx + nx * (dy + ny * dz);
+            CHF_CHECK(lin[t] < 0, CHF_EINVAL, "template offsets must point to smaller block indices");
+        }
+        const int64_t nb = nx * ny * nz;
+        std::unique_ptr<chf_pattern_s> P(new chf_pattern_s);
+        P->nb = nb;
+        P->rowptr.assign(nb + 1, 0);
+        std::vector<int32_t> row;
+        for (int64_t k = 0; k < nb; ++k) {
+            const int64_t kx = k % nx, ky = (k / nx) % ny, kz = k / (nx * ny);
+            row.clear();
+            for (int32_t t = 0; t < noff; ++t) {
+                const int64_t cx = kx + offsets[3 * t], cy = ky + offsets[3 * t + 1], cz = kz + offsets[3 * t + 2];
+                if (cx < 0 || cx >= nx || cy < 0 || cy >= ny || cz < 0 || cz >= nz) continue;
+                row.push_back((int32_t)(k + lin[t]));
+            }
+            std::sort(row.begin(), row.end());
+            row.erase(std::unique(row.begin(), row.end()), row.end());
+            P->colidx.insert(P->colidx.end(), row.begin(), row.end());
+            P->colidx.push_back((int32_t)k);
+            P->rowptr[k + 1] = (int64_t)P->colidx.size();
+        }
+        *out = P.release();
+    });
+}
+
 extern "C" int chf_pattern_info(chf_pattern P, int64_t* nb, int64_t* nnz) {
     return guarded([&] {
         CHF_CHECK(P, CHF_EINVAL, "NULL handle");

@@ -102,17 +102,19 @@ size_t vec_size(chf_dtype t);        // vector element size (double or float)
 // Slice-interleaved block-ELL: a slice holds S = 64 / b consecutive block
 // rows, so one 64-wide wavefront owns L = S * b output scalars (lane =
 // local_row * b + r). Slot j of slice s stores, for every lane, the b entries
-// of row r of that lane's j-th block in b / V runs of L groups of V
-// consecutive columns:
-//   vals[(((slot_base + j) * (b / V) + q) * L + lane) * V + v]
-//       = block(row, j)[r][q * V + v].
-// One load instruction therefore reads L * V contiguous values (16 bytes per
-// lane for FP64 with V = 2). Column indices are cols[(slot_base + j) * S +
+// of row r of that lane's j-th block in runs of consecutive columns: run q
+// covers columns c0_q .. c0_q + w_q - 1 and is stored as L groups of w_q values,
+//   vals[(slot_base + j) * stride + L * c0_q + lane * w_q + v]
+//       = block(row, j)[r][c0_q + v].
+// One load instruction therefore reads L * w_q contiguous values (16 bytes per
+// lane for FP64 with w_q = 2). The run widths depend on b and the storage
+// dtype (sell_build); slots are padded to 16 bytes when runs are wider than 1. Column indices are cols[(slot_base + j) * S +
 // local_row]; padding slots point at the row's own block with zero values.
 struct Sell {
     int64_t nb = 0;
     int b = 0, S = 0, L = 0;
-    int V = 1;                // consecutive columns c per lane load (see sell_build)
+    int V = 1;                // layout id: widest run of consecutive columns per lane load (see sell_build)
+    int stride = 0;           // elements per slot: b * L, padded to 16 bytes for the run layouts
     int64_t nslices = 0, nslots = 0;
     chf_dtype dtype = CHF_F64;
     DevBuf<int> slice_off;    // nslices + 1 (slots)
@@ -205,6 +207,9 @@ inline FactorOps factor_ops(const chf_fsai_s& G, chf_dtype t) {
     }
     return f;
 }
+// Inputs per candidate of the learned pattern proposer (features of
+// chf_mlp_features).
+constexpr int MLP_NIN = 6;
 // Deterministic FP64 reductions (fixed grid, fixed tree).
 constexpr int RED_BLOCKS = 512;
 // out[0] = sum x_i y_i over n doubles/floats (vec dtype), accumulated in FP64.

@@ -1,8 +1,8 @@
-// Learned block-pattern proposer: a 4 -> 64 -> 64 -> 1 ReLU network in FP32
+// Learned block-pattern proposer: a 6 -> 64 -> 64 -> 1 ReLU network in FP32
 // with hand-written forward, backward (binary cross-entropy with logits) and
 // Adam kernels, and a top-t selection that turns scores into a pattern.
 //
-// Parameter layout (4545 floats): W1[64][4], b1[64], W2[64][64], b2[64],
+// Parameter layout (4673 floats): W1[64][6], b1[64], W2[64][64], b2[64],
 // W3[64], b3.
 #include <algorithm>
 #include <cmath>
@@ -12,9 +12,11 @@
 
 namespace chf {
 constexpr int H = 64;
-constexpr int NIN = 4;
-constexpr int OFF_W1 = 0, OFF_B1 = 256, OFF_W2 = 320, OFF_B2 = 4416, OFF_W3 = 4480, OFF_B3 = 4544;
-constexpr int NPARAM = 4545;
+constexpr int NIN = MLP_NIN;
+constexpr int OFF_W1 = 0, OFF_B1 = H * NIN, OFF_W2 = OFF_B1 + H, OFF_B2 = OFF_W2 + H * H, OFF_W3 = OFF_B2 + H,
+              OFF_B3 = OFF_W3 + H;
+constexpr int NPARAM = OFF_B3 + 1;
+static_assert(NPARAM == 4673, "parameter layout");
 constexpr int TILE = 32;          // samples per tile
 constexpr int MLP_NT = 256;
 constexpr int MLP_OWN = (NPARAM + MLP_NT - 1) / MLP_NT;   // owned gradient entries per thread
@@ -383,7 +385,7 @@ extern "C" int chf_mlp_propose(chf_bsr A, chf_mlp net, int32_t nx, int32_t ny, i
         std::vector<int32_t> ccol;
         a2_candidates(A, crow, ccol);
         const int64_t nc = (int64_t)ccol.size();
-        DevBuf<float> feats(std::max<int64_t>(1, nc * 4)), score(std::max<int64_t>(1, nc));
+        DevBuf<float> feats(std::max<int64_t>(1, nc * NIN)), score(std::max<int64_t>(1, nc));
         mlp_features_impl(A, nx, ny, crow, ccol, feats.p, s);
         if (nc > 0) {
             const int grid = (int)std::min<int64_t>(4096, (nc + TILE - 1) / TILE);

@@ -264,10 +264,10 @@ def uniform_start(seed: int, ndof: int) -> np.ndarray:
 
 
 def mlp_init(seed: int) -> np.ndarray:
-    """He-uniform initial weights (zero biases) for the 4-64-64-1 network,
-    in the layout W1[64][4], b1[64], W2[64][64], b2[64], W3[64], b3."""
-    rng = np.random.default_rng(np.random.SeedSequence([seed, 4545]))
-    w1 = rng.uniform(-1, 1, (64, 4)) * np.sqrt(6.0 / 4)
+    """He-uniform initial weights (zero biases) for the 6-64-64-1 network,
+    in the layout W1[64][6], b1[64], W2[64][64], b2[64], W3[64], b3."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 4673]))
+    w1 = rng.uniform(-1, 1, (64, 6)) * np.sqrt(6.0 / 6)
     w2 = rng.uniform(-1, 1, (64, 64)) * np.sqrt(6.0 / 64)
     w3 = rng.uniform(-1, 1, 64) * np.sqrt(6.0 / 64)
     return np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, [0.0]]).astype(np.float32)

@@ -83,38 +83,70 @@ def test_c1_diag_gagt_identity(chf, c1):
         assert np.abs(s - np.eye(10)).max() < 1e-11
 
 
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    with open(path) as f:
+        return json.load(f)
+
+
 def test_c1_pcg_fp64_and_mixed(chf, c1):
-    """512x512, b = 10, 6 levels, adaptive t_max 8, V(4,4): FP64 PCG to 1e-8,
-    mixed FP32 and BF16-G within a few iterations of it."""
+    """512x512, b = 10, 6 levels, bilinear transfer, adaptive t_max 8, V(4,4):
+    FP64 PCG (Fletcher-Reeves) and the mixed forms (flexible PCG; A, G in FP32;
+    A in FP32 with G in BF16) each within one iteration of the oracle's count
+    for the same form (tests/golden/c1_pcg_iterations.json, written by
+    tests/golden/make_golden.py from the oracle alone), every level's adaptive
+    pattern bit-identical to the oracle's (SHA-256 of its CSR arrays) and the
+    Lanczos bounds within 1e-6 of the oracle's."""
+    import hashlib
+
     import torch
     p, a, _ = c1
+    gold = _golden("c1_pcg_iterations.json")["dirichlet"]
     b_ = dev(rhs(0, p.ndof))
-    its = {}
-    for dt, flex in [(0, False), (1, True), (2, True)]:
+    for dt, flex, name in [(0, False, "fp64"), (1, True, "mixed_f32"), (2, True, "mixed_bf16g")]:
         A, L, _, _ = gpu_levels(p, 6, 4, 1, tmax=8, dtype=dt)
+        if dt == 0:
+            for rec in gold["levels"]:
+                _, _, P = chf.levels_get(L, rec["level"])
+                prow, pcol = chf.pattern_export(P)
+                h = hashlib.sha256()
+                h.update(np.asarray(prow, dtype=np.int64).tobytes())
+                h.update(np.asarray(pcol, dtype=np.int64).tobytes())
+                assert h.hexdigest() == rec["pattern_sha256"], rec["level"]
+                beta = chf.levels_get_beta(L, rec["level"])
+                assert abs(beta - rec["beta"]) < 1e-6 * rec["beta"], (rec["level"], beta, rec["beta"])
         x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
         it, hist, tr, _ = chf.pcg_solve(L, b_, x, rtol=1e-8, maxit=200, flexible=flex)
+        want = gold["pcg"][name]["iterations"]
+        print(f"{name}: GPU {it} iterations, oracle {want}; recursive {hist[-1]:.2e}, true {tr:.2e}")
         assert hist[-1] <= 1e-8 and tr < 5e-8
-        its[dt] = it
+        assert abs(it - want) <= 1, (name, it, want)
         if dt == 0:   # bit-reproducible
             x2 = torch.zeros_like(x)
             it2, _, _, _ = chf.pcg_solve(L, b_, x2, rtol=1e-8, maxit=200)
             assert it2 == it and torch.equal(x, x2)
-    assert its[1] <= its[0] + 6 and its[2] <= its[0] + 10
 
 
 def test_c2_mixed_triharmonic_full_size(chf):
-    """256x256 patches, b = 21, D = L^3, 5 levels, adaptive t_max 8, A and G
-    in FP32 (and BF16 G), outer FP64 PCG to a recursive residual of 1e-10.
-    The patch-bilinear transfer is low order for a sixth-order operator, so
-    the cycle is not grid-independent (the oracle needs 17, 35, 74 iterations
-    at 16^2, 32^2, 64^2); a few hundred iterations are expected here."""
+    """256x256 patches, b = 21, D = L^3, 5 levels with the cubic patch
+    transfer, adaptive t_max 8, A and G in FP32 (and BF16 G), outer FP64 PCG
+    to a recursive residual of 1e-10. The iteration count stays within twice
+    the oracle's count on the 32x32 grid (the cycle is grid-independent with
+    this transfer), and the true residual is reported: 1e-10 lies below what
+    FP64 can resolve for this operator (about u ||A|| ||x|| / ||b||), so only
+    the recursive residual reaches it."""
     import torch
+    gold = _golden("c2_n32_pcg_iterations.json")["dirichlet"]["pcg"]
     p = make_problem(256, 2, 21, 3, seed=0)
     b_ = dev(rhs(0, p.ndof))
-    for dt in (1, 2):
-        A, L, _, _ = gpu_levels(p, 5, 4, 1, tmax=8, dtype=dt)
+    for dt, name in ((1, "mixed_f32"), (2, "mixed_bf16g")):
+        A, L, _, _ = gpu_levels(p, 5, 4, 1, tmax=8, dtype=dt, order=4)
         x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
-        it, hist, tr, _ = chf.pcg_solve(L, b_, x, rtol=1e-10, maxit=3000, flexible=True)
-        print(f"c2 dtype {dt}: {it} iterations, recursive {hist[-1]:.2e}, true {tr:.2e}")
+        it, hist, tr, _ = chf.pcg_solve(L, b_, x, rtol=1e-10, maxit=400, flexible=True)
+        print(f"c2 {name}: {it} iterations (oracle at 32^2: {gold[name]['iterations']}), "
+              f"recursive {hist[-1]:.2e}, true {tr:.2e}")
         assert hist[-1] <= 1e-10
+        assert it <= 2 * gold[name]["iterations"]
+        assert tr < 1e-3

@@ -33,12 +33,13 @@ def test_features_match_oracle(chf, n, dim, b):
     crow, ccol = chf.mlp_candidates(A)
     ocrow, occol = mlp.a2_candidates(a)
     assert np.array_equal(crow, ocrow) and np.array_equal(ccol, occol)
-    f = torch.zeros(len(ccol) * 4, dtype=torch.float32, device="cuda")
+    f = torch.zeros(len(ccol) * mlp.NIN, dtype=torch.float32, device="cuda")
     chf.mlp_features(A, n, n, f)
-    got = host(f).reshape(-1, 4)
+    got = host(f).reshape(-1, mlp.NIN)
     _, _, want = mlp.features(a, n, n)
     ref = np.concatenate([want[k][1] for k in range(p.nb)])
-    for j in range(4):
+    assert np.array_equal(got[:, 2:5], ref[:, 2:5])        # grid offsets, exact
+    for j in (0, 1, 5):
         assert rel_err(got[:, j], ref[:, j]) < 1e-5, j
 
 
@@ -46,9 +47,10 @@ def test_forward_and_gradient_match_oracle(chf):
     import torch
     rng = np.random.default_rng(0)
     params = mlp_init(7)
-    params[256:320] = (0.1 * rng.standard_normal(64)).astype(np.float32)
+    o1 = mlp.H * mlp.NIN
+    params[o1:o1 + 64] = (0.1 * rng.standard_normal(64)).astype(np.float32)
     n = 1000
-    x = rng.standard_normal((n, 4)).astype(np.float32)
+    x = rng.standard_normal((n, mlp.NIN)).astype(np.float32)
     y = (rng.uniform(size=n) < 0.3).astype(np.float32)
     net = chf.mlp_create(params)
     assert np.array_equal(chf.mlp_get_params(net), params)
@@ -57,7 +59,7 @@ def test_forward_and_gradient_match_oracle(chf):
     chf.mlp_forward(net, xd, n, logits)
     want, _ = mlp.forward(params.astype(np.float64), x.astype(np.float64))
     assert rel_err(host(logits), want) < 1e-5
-    g = torch.zeros(4545, dtype=torch.float32, device="cuda")
+    g = torch.zeros(mlp.NPARAM, dtype=torch.float32, device="cuda")
     loss = chf.mlp_loss_grad(net, xd, dev(y), n, g)
     wl, wg = mlp.loss_grad(params.astype(np.float64), x.astype(np.float64), y.astype(np.float64))
     assert abs(loss - wl) < 1e-5 * abs(wl)
@@ -68,7 +70,7 @@ def test_training_reduces_loss_and_is_deterministic(chf):
     import torch
     rng = np.random.default_rng(1)
     n = 20000
-    x = rng.standard_normal((n, 4)).astype(np.float32)
+    x = rng.standard_normal((n, mlp.NIN)).astype(np.float32)
     y = (x[:, 0] + 0.5 * x[:, 3] > 0.2).astype(np.float32)
     perm = dev(permutation(0, n))
     outs = []
@@ -95,7 +97,7 @@ def test_labels_and_proposal(chf):
     net = chf.mlp_create(mlp_init(2))
     Q = chf.mlp_propose(A, net, n, n, 4)
     qrow, qcol = chf.pattern_export(Q)
-    f = torch.zeros(len(ccol) * 4, dtype=torch.float32, device="cuda")
+    f = torch.zeros(len(ccol) * mlp.NIN, dtype=torch.float32, device="cuda")
     chf.mlp_features(A, n, n, f)
     s = torch.zeros(len(ccol), dtype=torch.float32, device="cuda")
     chf.mlp_forward(net, f, len(ccol), s)
@@ -117,13 +119,16 @@ def test_labels_and_proposal(chf):
 
 def test_learned_pattern_gain_over_adaptive(chf):
     """Train on seeds 1-8 (64x64 2D and 12^3 3D grids, labels from Algorithm 1
-    with t_max = 8), test on a 128x128 grid with seed 100: the proposal must
-    be cheaper to form than Algorithm 1's pattern and give a V-cycle whose
-    energy-norm convergence factor is within 10 % of the adaptive one."""
+    with t_max = 8), test on a 256x256 grid with seed 100. The gain claimed
+    for the network: its proposal is formed in less time than Algorithm 1's
+    pattern (best of 3 calls each) and gives a V(4,4) cycle whose energy-norm
+    convergence factor is within 5 % of the adaptive one. The interior
+    template is reported beside both."""
     import torch
     from paper_2509_06744_amd import learned
     from tests.helpers import gpu_levels
     items, keep = [], []
+    tmpl = None
     for seed in range(1, 9):
         for n, dim in [(64, 2), (12, 3)]:
             p = make_problem(n, dim, 10, 2, seed=seed)
@@ -131,24 +136,41 @@ def test_learned_pattern_gain_over_adaptive(chf):
             P = chf.pattern_adaptive(A, 8)
             items.append((A, n, n, P))
             keep.append((A, P))
+            if tmpl is None and dim == 2:
+                rp, cp = chf.pattern_export(P)
+                tmpl = learned.template_offsets(rp, cp, n, n, (n // 2) * n + n // 2)
     X, Y = learned.dataset(items)
     net, hist = learned.train(X, Y, mlp_init(0), dev(permutation(0, Y.shape[0])), epochs=4, batch=4096)
     assert hist[-1] < hist[0]
-    n = 128
+    n = 256
     p = make_problem(n, 2, 10, 2, seed=100)
     A = upload(p)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Pa = chf.pattern_adaptive(A, 8)
-    t_ad = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    Pl = chf.mlp_propose(A, net, n, n, 8)
-    t_ml = time.perf_counter() - t0
+
+    def best_time(make):
+        best, out = None, None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = make()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        return best, out
+    t_ad, Pa = best_time(lambda: chf.pattern_adaptive(A, 8))
+    t_ml, Pl = best_time(lambda: chf.mlp_propose(A, net, n, n, 8))
+    t_tp, Pt = best_time(lambda: chf.pattern_template(n, n, 1, tmpl))
+    ra, ca = chf.pattern_export(Pa)
+    same = {}
+    for name, P in [("learned", Pl), ("template", Pt)]:
+        rl, cl = chf.pattern_export(P)
+        same[name] = np.mean([np.array_equal(ca[ra[k]:ra[k + 1]], cl[rl[k]:rl[k + 1]]) for k in range(p.nb)])
     e0 = dev(uniform_start(100, p.ndof))
     rho = {}
-    for name, P in [("adaptive", Pa), ("learned", Pl)]:
+    for name, P in [("adaptive", Pa), ("learned", Pl), ("template", Pt)]:
         # level 0 takes the given pattern, coarser levels Algorithm 1 (t_max 8)
-        A0, L, _, _ = gpu_levels(p, 4, 4, 1, tmax=8, level0_pattern=P)
+        A0, L, _, _ = gpu_levels(p, 5, 4, 1, tmax=8, level0_pattern=P)
         rho[name], _ = chf.levels_energy_factor(L, e0)
-    print(f"pattern time adaptive {t_ad * 1e3:.1f} ms, learned {t_ml * 1e3:.1f} ms; rho_A {rho}")
-    assert rho["learned"] <= 1.10 * rho["adaptive"]
+    print(f"pattern time adaptive {t_ad * 1e3:.1f} ms, learned {t_ml * 1e3:.1f} ms, template {t_tp * 1e3:.1f} ms; "
+          f"rows identical to Algorithm 1: {same}; rho_A {rho}")
+    assert t_ml < t_ad
+    assert rho["learned"] <= 1.05 * rho["adaptive"]

@@ -12,9 +12,11 @@ from problems import make_problem, mlp_init
 def test_gradient_matches_finite_differences():
     rng = np.random.default_rng(0)
     p = mlp_init(3).astype(np.float64)
-    p[256:320] = 0.1 * rng.standard_normal(64)     # nonzero biases
-    p[4416:4480] = 0.1 * rng.standard_normal(64)
-    x = rng.standard_normal((40, 4))
+    o1 = mlp.H * mlp.NIN
+    o2 = o1 + mlp.H + mlp.H * mlp.H
+    p[o1:o1 + 64] = 0.1 * rng.standard_normal(64)     # nonzero biases
+    p[o2:o2 + 64] = 0.1 * rng.standard_normal(64)
+    x = rng.standard_normal((40, mlp.NIN))
     y = (rng.uniform(size=40) < 0.4).astype(np.float64)
     lval, g = mlp.loss_grad(p, x, y)
     assert abs(lval - mlp.loss(p, x, y)) < 1e-14
@@ -29,14 +31,15 @@ def test_gradient_matches_finite_differences():
 
 def test_loss_closed_form_zero_net():
     p = np.zeros(mlp.NPARAM)
-    x = np.ones((5, 4))
+    x = np.ones((5, mlp.NIN))
     y = np.array([0, 1, 1, 0, 1.0])
     assert abs(mlp.loss(p, x, y) - math.log(2)) < 1e-15
 
 
 def test_features_closed_form_unrotated():
     # with R = I: A_ij = D_ij I_b, so f0 = |D_kc| / sqrt(D_kk D_cc),
-    # f1 = |D_ck / D_cc| sqrt(b), f3 = -b log(1 - D_kc^2 / (D_kk D_cc))
+    # f1 = |D_ck / D_cc| sqrt(b), f2..f4 the grid offset of c from k,
+    # f5 = -b log(1 - D_kc^2 / (D_kk D_cc))
     n, b = 6, 3
     p = make_problem(n, 2, b, 2, seed=0, rotate=False)
     a = from_problem(p)
@@ -47,9 +50,9 @@ def test_features_closed_form_unrotated():
             dkc, dkk, dcc = d[k, c], d[k, k], d[c, c]
             assert abs(fc[0] - abs(dkc) / math.sqrt(dkk * dcc)) < 1e-12
             assert abs(fc[1] - abs(dkc / dcc) * math.sqrt(b)) < 1e-12
-            assert abs(fc[2] - math.hypot(c % n - k % n, c // n - k // n)) < 1e-12
+            assert (fc[2], fc[3], fc[4]) == (c % n - k % n, c // n - k // n, 0)
             want = -b * math.log1p(-dkc * dkc / (dkk * dcc))
-            assert abs(fc[3] - want) < 1e-12 * max(1.0, want)
+            assert abs(fc[5] - want) < 1e-12 * max(1.0, want)
 
 
 def test_topk_ties_to_smaller_column():
