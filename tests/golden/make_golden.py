@@ -28,11 +28,16 @@ to _work/ instead of the golden file).
 """
 from __future__ import annotations
 
+import os
+
+# one BLAS thread per worker process: the pool supplies the parallelism
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
 import argparse
 import hashlib
 import json
 import multiprocessing as mp
-import os
 import sys
 import time
 
