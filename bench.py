@@ -725,7 +725,7 @@ def main():
             if Hh is not H:
                 Hh.destroy()
         if n == 512 and L == 6 and k == 4 and args.tmax == 8 and os.path.exists(GOLDEN_C1):
-            gold = json.load(open(GOLDEN_C1))["pcg"]
+            gold = json.load(open(GOLDEN_C1))["dirichlet"]["pcg"]
             for name in ("fp64", "mixed_f32", "mixed_bf16g"):
                 if name in gold:
                     res[name]["oracle_iterations"] = gold[name]["iterations"]

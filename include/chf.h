@@ -86,6 +86,30 @@ int chf_bsr_export(chf_bsr A, int64_t* rowptr, int32_t* colidx, double* vals);
 int chf_bsr_spmv(chf_bsr A, chf_dtype dtype, const void* x, const void* bvec, void* y,
                  int residual, hipStream_t stream);
 
+/* -------------------------------------------------- variable block sizes -- */
+/* Block-sparse SPD matrix whose blocks have their own sizes m_i = bsize[i]
+ * (Def. 2.1's block structure with unequal blocks, e.g. a higher polynomial
+ * degree on the boundary patches, Sec. 5 Ex. 5.1). rowptr/colidx as for
+ * chf_bsr_create; block e = (i, colidx[e]) is the bsize[i] x bsize[colidx[e]]
+ * array stored row-major at vals + voff_e, voff_e being the running sum of
+ * bsize[i] * bsize[colidx[e]] over the preceding blocks in storage order. All
+ * arrays are host arrays, copied; 1 <= bsize[i] <= 64; EINVAL on bad
+ * structure or non-finite values. The handle is a chf_bsr whose vectors have
+ * sum(bsize) entries. Accepted with CHF_F64: chf_bsr_spmv, chf_pattern_lower,
+ * chf_fsai_setup (local systems of at most 32 blocks and 160 unknowns, own
+ * block at most 16 wide; EINVAL beyond), chf_fsai_apply, chf_fsai_export
+ * (G's blocks bsize[k] x bsize[j] in pattern order, flat), chf_lmax_lanczos
+ * and the smoothers (chf_cheb4_smooth[_noalloc], chf_cheb1_smooth,
+ * chf_richardson_smooth). The adaptive pattern, nested FSAI, the hierarchy,
+ * the learned proposer and FP32/BF16 storage take uniform blocks only
+ * (EINVAL). chf_bsr_info reports b = the largest block; chf_bsr_export
+ * writes the flat values. */
+int chf_vbsr_create(int64_t nb, const int32_t* bsize, const int64_t* rowptr, const int32_t* colidx,
+                    const double* vals, chf_bsr* out);
+/* Unknowns, stored values and block sizes (host int32[nb], may be NULL) of a
+ * matrix, uniform or not. */
+int chf_vbsr_info(chf_bsr A, int64_t* ndof, int64_t* nvals, int32_t* bsize);
+
 /* ------------------------------------------------------------ patterns ---- */
 /* Lower block triangle of A with the diagonal (static pattern, Sec. 2.1). */
 int chf_pattern_lower(chf_bsr A, chf_pattern* out);

@@ -10,9 +10,9 @@ __all__ = [
     "F64", "F32", "BF16", "NFEAT", "NPARAM", "SMOOTH_CHEB4", "SMOOTH_CHEB1", "SMOOTH_RICHARDSON", "CYCLE_VKK", "CYCLE_V2K0",
     "ChfError", "lib", "lib_path", "version", "current_stream",
     "Bsr", "Pattern", "Fsai", "Levels", "Mlp", "LevelOpts",
-    "bsr_create", "bsr_export", "bsr_spmv",
+    "bsr_create", "bsr_export", "bsr_spmv", "vbsr_create", "vbsr_info",
     "pattern_lower", "pattern_from_csr", "pattern_adaptive", "pattern_template", "pattern_export",
-    "fsai_setup", "fsai_export", "fsai_apply", "bsr_triple", "fsai_nest", "lmax_lanczos",
+    "fsai_setup", "fsai_export", "fsai_export_flat", "fsai_apply", "bsr_triple", "fsai_nest", "lmax_lanczos",
     "cheb4_smooth", "cheb4_smooth_noalloc", "cheb1_smooth", "richardson_smooth",
     "levels_create", "levels_add_coarse", "levels_setup", "levels_get", "levels_get_beta",
     "levels_set_beta", "levels_set_cycle", "levels_set_nesting", "levels_info", "levels_set_pattern", "vcycle", "pcg_solve",
@@ -48,6 +48,8 @@ EXPORTED = {
     "chf_version": (C.c_char_p, []),
     "chf_bsr_create": (C.c_int, [_i64, _i32, _vp, _vp, _vp, C.c_int, C.POINTER(_vp)]),
     "chf_bsr_destroy": (C.c_int, [_vp]),
+    "chf_vbsr_create": (C.c_int, [_i64, _vp, _vp, _vp, _vp, C.POINTER(_vp)]),
+    "chf_vbsr_info": (C.c_int, [_vp, _pi64, _pi64, _vp]),
     "chf_bsr_info": (C.c_int, [_vp, _pi64, _pi32, _pi64]),
     "chf_bsr_export": (C.c_int, [_vp, _vp, _vp, _vp]),
     "chf_bsr_spmv": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp, C.c_int, _vp]),
@@ -221,6 +223,26 @@ def bsr_create(nb, b, rowptr, colidx, vals):
     return Bsr(out)
 
 
+def vbsr_create(nb, bsize, rowptr, colidx, vals):
+    """Variable block sizes: bsize int32[nb]; vals flat, block by block."""
+    bs, bsp = _host(bsize, np.int32)
+    rp, rpp = _host(rowptr, np.int64)
+    ci, cip = _host(colidx, np.int32)
+    vv, vvp = _host(vals, np.float64)
+    out = C.c_void_p()
+    _check(_fn("chf_vbsr_create")(int(nb), bsp, rpp, cip, vvp, C.byref(out)))
+    return Bsr(out)
+
+
+def vbsr_info(A: Bsr):
+    """Returns (unknowns, stored values, block sizes int32[nb])."""
+    nb = A.info()[0]
+    nd, nv = C.c_int64(), C.c_int64()
+    bs = np.empty(nb, np.int32)
+    _check(_fn("chf_vbsr_info")(A.h, C.byref(nd), C.byref(nv), bs.ctypes.data_as(C.c_void_p)))
+    return nd.value, nv.value, bs
+
+
 def bsr_export(A: Bsr):
     nb, b, nnzb = A.info()
     rowptr = np.empty(nb + 1, np.int64)
@@ -305,6 +327,13 @@ def fsai_nest(G0: Fsai, G1: Fsai) -> Fsai:
 
 def fsai_export(G: Fsai, nnz: int, b: int):
     vals = np.empty((nnz, b, b), np.float64)
+    _check(_fn("chf_fsai_export")(G.h, vals.ctypes.data_as(C.c_void_p)))
+    return vals
+
+
+def fsai_export_flat(G: Fsai, nvals: int):
+    """G's values as one flat array (variable block sizes: nvals values)."""
+    vals = np.empty(nvals, np.float64)
     _check(_fn("chf_fsai_export")(G.h, vals.ctypes.data_as(C.c_void_p)))
     return vals
 

@@ -991,6 +991,7 @@ static void ai_launch(int64_t grid, size_t dyn, hipStream_t s, int64_t nb, int b
 
 chf_pattern_s* adaptive_pattern_impl(chf_bsr A, const chf_pattern_s* P0, int tmax, double tau, hipStream_t s) {
     CHF_CHECK(tau > 0.0 && tau <= 1.0, CHF_EINVAL, "tau must be in (0, 1]");
+    CHF_CHECK(!A->vb, CHF_EINVAL, "the adaptive pattern supports uniform block sizes only");
     const int64_t nb = A->nb;
     const int b = A->b;
     int maxp0 = 1;   // blocks per row of P0 (diagonal when P0 is NULL)
@@ -1258,6 +1259,7 @@ void mlp_features_impl(chf_bsr A, int nx, int ny, const std::vector<int64_t>& cr
 
 extern "C" int chf_mlp_candidates(chf_bsr A, int64_t* ncand, int64_t* rowptr, int32_t* cols) {
     return chf::guarded([&] {
+        CHF_CHECK(!A || !A->vb, CHF_EINVAL, "the learned proposer supports uniform block sizes only");
         CHF_CHECK(A && ncand, CHF_EINVAL, "NULL argument");
         std::vector<int64_t> r;
         std::vector<int32_t> c;
@@ -1270,6 +1272,7 @@ extern "C" int chf_mlp_candidates(chf_bsr A, int64_t* ncand, int64_t* rowptr, in
 
 extern "C" int chf_mlp_features(chf_bsr A, int32_t nx, int32_t ny, float* feats, hipStream_t stream) {
     return chf::guarded([&] {
+        CHF_CHECK(!A || !A->vb, CHF_EINVAL, "the learned proposer supports uniform block sizes only");
         CHF_CHECK(A && feats, CHF_EINVAL, "NULL argument");
         CHF_CHECK(nx >= 1 && ny >= 1 && A->nb % ((int64_t)nx * ny) == 0, CHF_EINVAL, "grid does not match nb");
         std::vector<int64_t> r;

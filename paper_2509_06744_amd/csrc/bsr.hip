@@ -130,6 +130,7 @@ static int sell_vec_width(int b, chf_dtype t) {
 void sell_build(Sell& out, const SellPlan& plan, const double* d_src_blocks, bool transpose,
                 chf_dtype dtype, hipStream_t s) {
     out.nb = plan.nb;
+    out.ndof = plan.nb * (int64_t)plan.b;
     out.b = plan.b;
     out.S = plan.S;
     out.L = plan.L;
@@ -540,6 +541,10 @@ static void launch_spmv_b(const Sell& A, const void* x, void* y, const void* bv,
 
 void sell_spmv(const Sell& A, chf_dtype vec, const void* x, void* y, const void* bvec, int epi, void* p,
                void* xo, double alpha, double beta, hipStream_t s) {
+    if (A.vb) {
+        vsell_spmv(A, vec, x, y, bvec, epi, p, xo, alpha, beta, s);
+        return;
+    }
     if (A.dtype == CHF_F64) {
         CHF_CHECK(vec == CHF_F64, CHF_EINVAL, "FP64 operator needs FP64 vectors");
         launch_spmv_b<double, double>(A, x, y, bvec, epi, p, xo, alpha, beta, s);
@@ -598,6 +603,7 @@ using namespace chf;
 
 const Sell& chf_bsr_s::sell(chf_dtype t, hipStream_t s) {
     if (t == CHF_F64) return sell64;
+    CHF_CHECK(!vb, CHF_EINVAL, "variable block sizes: FP64 only");
     if (sell32.nslices == 0 && nb > 0) sell_build(sell32, plan, d_vals.p, false, CHF_F32, s);
     return sell32;
 }
@@ -623,6 +629,7 @@ extern "C" int chf_bsr_create(int64_t nb, int32_t b, const int64_t* rowptr, cons
         std::unique_ptr<chf_bsr_s> A(new chf_bsr_s);
         A->nb = nb;
         A->b = b;
+        A->ndof = nb * (int64_t)b;
         A->nnzb = nnzb;
         A->rowptr.assign(rowptr, rowptr + nb + 1);
         A->colidx.assign(colidx, colidx + nnzb);
@@ -666,7 +673,8 @@ extern "C" int chf_bsr_export(chf_bsr A, int64_t* rowptr, int32_t* colidx, doubl
         if (rowptr) std::memcpy(rowptr, A->rowptr.data(), (A->nb + 1) * 8);
         if (colidx) std::memcpy(colidx, A->colidx.data(), A->nnzb * 4);
         if (vals) {
-            A->d_vals.download(vals, (size_t)A->nnzb * A->b * A->b, 0);
+            const size_t nv = A->vb ? (size_t)A->voff[A->nnzb] : (size_t)A->nnzb * A->b * A->b;
+            A->d_vals.download(vals, nv, 0);
             CHF_HIP(hipStreamSynchronize(0));
         }
     });
@@ -678,6 +686,7 @@ extern "C" int chf_bsr_spmv(chf_bsr A, chf_dtype dtype, const void* x, const voi
         CHF_CHECK(A && x && y, CHF_EINVAL, "NULL argument");
         CHF_CHECK(!residual || bvec, CHF_EINVAL, "residual needs bvec");
         CHF_CHECK(dtype == CHF_F64 || dtype == CHF_F32, CHF_EINVAL, "vector dtype must be F64 or F32");
+        CHF_CHECK(!A->vb || dtype == CHF_F64, CHF_EINVAL, "variable block sizes: FP64 only");
         const Sell& S = A->sell(dtype, stream);
         sell_spmv(S, dtype, x, y, bvec, residual ? EPI_RES : EPI_AX, nullptr, nullptr, 0, 0, stream);
     });

@@ -811,8 +811,9 @@ __global__ void k_scale_by_rsqrt(int64_t n, const double* __restrict__ x, double
 
 void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const double* v0, double safety,
                   double* beta_out, double* theta_out, hipStream_t s) {
-    const int64_t n = A->nb * (int64_t)A->b;
+    const int64_t n = A->ndof;
     CHF_CHECK(iters >= 1, CHF_EINVAL, "iters must be >= 1");
+    CHF_CHECK(!A->vb || dt == CHF_F64, CHF_EINVAL, "variable block sizes: FP64 only");
     const int m = (int)std::min<int64_t>(iters, n);
     const Sell& sa = A->sell(dt == CHF_F64 ? CHF_F64 : CHF_F32, s);
     const FactorOps fo = factor_ops(G, dt);
@@ -977,6 +978,11 @@ extern "C" int chf_fsai_setup(chf_bsr A, chf_pattern P, chf_dtype g_store, chf_f
         CHF_CHECK(g_store == CHF_F64 || g_store == CHF_F32 || g_store == CHF_BF16, CHF_EINVAL, "bad dtype");
         *out = nullptr;
         if (bad_row) *bad_row = -1;
+        if (A->vb) {
+            CHF_CHECK(g_store == CHF_F64, CHF_EINVAL, "variable block sizes: FP64 only");
+            *out = vfsai_setup_impl(A, *P, bad_row, 0);
+            return;
+        }
         *out = fsai_setup_impl(A, *P, g_store, bad_row, 0);
     });
 }
@@ -989,7 +995,7 @@ extern "C" int chf_fsai_export(chf_fsai G, double* vals) {
     return guarded([&] {
         CHF_CHECK(G && vals, CHF_EINVAL, "NULL argument");
         CHF_CHECK(!G->nest_outer, CHF_EINVAL, "nested factor: export its outer and inner factors");
-        G->d_vals.download(vals, (size_t)G->nnz * G->b * G->b, 0);
+        G->d_vals.download(vals, G->vb ? (size_t)G->voff[G->nnz] : (size_t)G->nnz * G->b * G->b, 0);
         CHF_HIP(hipStreamSynchronize(0));
     });
 }

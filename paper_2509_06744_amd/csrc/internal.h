@@ -110,8 +110,11 @@ size_t vec_size(chf_dtype t);        // vector element size (double or float)
 // lane for FP64 with w_q = 2). The run widths depend on b and the storage
 // dtype (sell_build); slots are padded to 16 bytes when runs are wider than 1. Column indices are cols[(slot_base + j) * S +
 // local_row]; padding slots point at the row's own block with zero values.
+struct VSellLayout;   // variable block sizes (vbsr.hip)
+
 struct Sell {
     int64_t nb = 0;
+    int64_t ndof = 0;         // rows of the matrix in unknowns (nb * b for uniform blocks)
     int b = 0, S = 0, L = 0;
     int V = 1;                // layout id: widest run of consecutive columns per lane load (see sell_build)
     int stride = 0;           // elements per slot: b * L, padded to 16 bytes for the run layouts
@@ -120,6 +123,7 @@ struct Sell {
     DevBuf<int> slice_off;    // nslices + 1 (slots)
     DevBuf<int> cols;         // nslots * S
     DevBuf<char> vals;        // nslots * b * L elements of dtype
+    std::shared_ptr<VSellLayout> vb;   // set for variable block sizes (then the fields above are unused)
 };
 
 // Host description of a block-sparse structure with a map from each stored
@@ -146,13 +150,25 @@ enum Epi { EPI_AX = 0, EPI_RES = 1, EPI_CHEB_FIRST0 = 2, EPI_CHEB_FIRST = 3, EPI
 // read in its own storage dtype and accumulated in the vector's precision.
 void sell_spmv(const Sell& A, chf_dtype vec, const void* x, void* y, const void* bvec, int epi,
                void* p, void* xo, double alpha, double beta, hipStream_t s);
+// The same for the variable-block layout (vbsr.hip; FP64 only).
+void vsell_spmv(const Sell& A, chf_dtype vec, const void* x, void* y, const void* bvec, int epi,
+                void* p, void* xo, double alpha, double beta, hipStream_t s);
 
 // ------------------------------------------------------------------ handles --
 }  // namespace chf
 
 struct chf_bsr_s {
     int64_t nb = 0, nnzb = 0;
-    int b = 0;
+    int b = 0;                          // block size (the largest one with variable blocks)
+    int64_t ndof = 0;                   // unknowns: nb * b, or the sum of the block sizes
+    // variable block sizes (chf_vbsr_create): block e = (i, j) is the
+    // bsize[i] x bsize[j] array at d_vals + voff[e]; unknowns of block row i
+    // start at boff[i]
+    bool vb = false;
+    std::vector<int32_t> bsize;
+    std::vector<int64_t> boff, voff;
+    chf::DevBuf<int64_t> d_voff;        // device copies (variable block sizes only)
+    chf::DevBuf<int> d_bsize;
     std::vector<int64_t> rowptr;        // host structure
     std::vector<int32_t> colidx;
     chf::DevBuf<int> d_rowptr;          // device plain BSR (FP64) for set-up kernels
@@ -173,6 +189,11 @@ struct chf_pattern_s {
 struct chf_fsai_s {
     int64_t nb = 0, nnz = 0;
     int b = 0;
+    // variable block sizes: G's block e = (k, j) is bsize[k] x bsize[j] at
+    // d_vals + voff[e] (uniform blocks: voff empty, e * b * b)
+    bool vb = false;
+    std::vector<int32_t> bsize;
+    std::vector<int64_t> voff;
     chf_dtype store = CHF_F64;
     std::vector<int64_t> rowptr;        // pattern (lower)
     std::vector<int32_t> colidx;
@@ -210,6 +231,8 @@ inline FactorOps factor_ops(const chf_fsai_s& G, chf_dtype t) {
 // Inputs per candidate of the learned pattern proposer (features of
 // chf_mlp_features).
 constexpr int MLP_NIN = 6;
+// Block-FSAI factor of a variable-block matrix (vbsr.hip).
+chf_fsai_s* vfsai_setup_impl(chf_bsr A, const chf_pattern_s& P, int64_t* bad_row, hipStream_t s);
 // Deterministic FP64 reductions (fixed grid, fixed tree).
 constexpr int RED_BLOCKS = 512;
 // out[0] = sum x_i y_i over n doubles/floats (vec dtype), accumulated in FP64.

@@ -686,6 +686,7 @@ static void alloc_vectors(chf_levels_s& H) {
 extern "C" int chf_levels_create(chf_bsr A0, chf_levels* out) {
     return guarded([&] {
         CHF_CHECK(A0 && out, CHF_EINVAL, "NULL argument");
+        CHF_CHECK(!A0->vb, CHF_EINVAL, "the hierarchy supports uniform block sizes only");
         std::unique_ptr<chf_levels_s> H(new chf_levels_s);
         H->lev.emplace_back();
         H->lev[0].A = A0;

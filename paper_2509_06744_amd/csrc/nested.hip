@@ -114,6 +114,7 @@ chf_bsr_s* bsr_triple_impl(chf_bsr A, const chf_fsai_s& G, hipStream_t s) {
     std::unique_ptr<chf_bsr_s> C(new chf_bsr_s);
     C->nb = nb;
     C->b = b;
+    C->ndof = nb * (int64_t)b;
     C->rowptr.assign(nb + 1, 0);
     std::vector<int64_t> cpp(1, 0);
     std::vector<int32_t> cpx, cpy;
@@ -208,6 +209,7 @@ extern "C" int chf_bsr_triple(chf_bsr A, chf_fsai G, chf_bsr* out) {
         CHF_CHECK(A && G && out, CHF_EINVAL, "NULL argument");
         *out = nullptr;
         CHF_CHECK(!G->nest_outer, CHF_EINVAL, "G is a nested factor: pass its outer factor");
+        CHF_CHECK(!A->vb && !G->vb, CHF_EINVAL, "nested FSAI supports uniform block sizes only");
         CHF_CHECK(A->nb == G->nb && A->b == G->b, CHF_EINVAL, "A and G sizes differ");
         *out = bsr_triple_impl(A, *G, 0);
     });
@@ -218,6 +220,7 @@ extern "C" int chf_fsai_nest(chf_fsai G0, chf_fsai G1, chf_fsai* out) {
         CHF_CHECK(G0 && G1 && out, CHF_EINVAL, "NULL argument");
         *out = nullptr;
         CHF_CHECK(!G0->nest_outer && !G1->nest_outer, CHF_EINVAL, "one nesting level only");
+        CHF_CHECK(!G0->vb && !G1->vb, CHF_EINVAL, "nested FSAI supports uniform block sizes only");
         CHF_CHECK(G0->nb == G1->nb && G0->b == G1->b, CHF_EINVAL, "G0 and G1 sizes differ");
         CHF_CHECK(G0->store == G1->store, CHF_EINVAL, "G0 and G1 storage dtypes differ");
         std::unique_ptr<chf_fsai_s> N(new chf_fsai_s);

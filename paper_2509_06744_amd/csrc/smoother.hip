@@ -82,7 +82,7 @@ static void poly_smooth_impl(const Sell& A, const Sell& G, const Sell& Gt, const
                              chf_dtype vec, const StepCoef& cf, const void* b, void* x, bool x_is_zero, void* work,
                              hipStream_t s) {
     const int k = (int)cf.c.size();
-    const int64_t n = A.nb * (int64_t)A.b;
+    const int64_t n = A.ndof;
     const size_t es = vec_size(vec);
     char* w = static_cast<char*>(work);
     void* r = w;
@@ -145,7 +145,7 @@ int with_operands(chf_bsr A, chf_fsai G, chf_dtype dtype, const void* b, void* x
                   F&& f) {
     return guarded([&] {
         CHF_CHECK(A && G && b && x && work, CHF_EINVAL, "NULL argument");
-        CHF_CHECK(A->nb == G->nb && A->b == G->b, CHF_EINVAL, "A and G sizes differ");
+        CHF_CHECK(A->nb == G->nb && A->b == G->b && A->vb == G->base().vb, CHF_EINVAL, "A and G sizes differ");
         CHF_CHECK(dtype == CHF_F64 || dtype == G->store, CHF_EINVAL,
                   "dtype must be F64 or the factor's storage dtype");
         chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
@@ -188,15 +188,16 @@ extern "C" int chf_cheb4_smooth_noalloc(chf_bsr A, chf_fsai G, chf_dtype dtype, 
                                         const void* b, void* x, int x_is_zero, hipStream_t stream) {
     return guarded([&] {
         CHF_CHECK(A && G && b && x, CHF_EINVAL, "NULL argument");
-        CHF_CHECK(A->nb == G->nb && A->b == G->b, CHF_EINVAL, "A and G sizes differ");
+        CHF_CHECK(A->nb == G->nb && A->b == G->b && A->vb == G->base().vb, CHF_EINVAL, "A and G sizes differ");
         CHF_CHECK(dtype == CHF_F64 || dtype == G->store, CHF_EINVAL,
                   "dtype must be F64 or the factor's storage dtype");
         const chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
-        const int64_t n = A->nb * (int64_t)A->b;
+        const int64_t n = A->ndof;
         CHF_CHECK((size_t)n * 3 * vec_size(vec) <= kNoallocScratchBytes, CHF_EINVAL,
                   "chf_cheb4_smooth_noalloc: 3 vectors of " + std::to_string(n) +
                       " elements exceed its 64 MiB scratch");
         // the FP32 layout of A is built on first use, which allocates
+        CHF_CHECK(vec == CHF_F64 || !A->vb, CHF_EINVAL, "variable block sizes: FP64 only");
         CHF_CHECK(vec == CHF_F64 || A->nb == 0 || A->sell32.nslices > 0, CHF_EINVAL,
                   "chf_cheb4_smooth_noalloc: the FP32 layout of A does not exist yet (make one FP32 call of "
                   "chf_cheb4_smooth or chf_bsr_spmv first)");

@@ -8,6 +8,9 @@ use it.
 """
 from .generator import (  # noqa: F401
     Problem,
+    VarProblem,
+    make_vb_problem,
+    vb_block_sizes,
     laplacian,
     stencil_matrix,
     make_problem,

@@ -151,6 +151,86 @@ def make_problem(n: int, dim: int, b: int, power: int, seed: int = 0,
                    colidx=colidx, vals=vals, dstencil=dmat, rfac=rfac, rinv=rinv)
 
 
+@dataclass
+class VarProblem:
+    """Block-sparse SPD matrix with variable block sizes m_i (Def. 2.1's block
+    structure with unequal blocks). Block e = (i, j) is the m_i x m_j array
+    vals[voff[e]:voff[e+1]] in row-major order."""
+
+    n: int
+    dim: int
+    power: int
+    seed: int
+    bsize: np.ndarray      # int32, nb: m_i
+    rowptr: np.ndarray     # int64, nb+1
+    colidx: np.ndarray     # int32, nnzb (ascending within each row)
+    vals: np.ndarray       # float64, sum over stored blocks of m_i m_j
+    voff: np.ndarray       # int64, nnzb+1
+    dstencil: sp.csr_matrix = field(repr=False)
+
+    @property
+    def nb(self) -> int:
+        return int(self.rowptr.shape[0] - 1)
+
+    @property
+    def nnzb(self) -> int:
+        return int(self.colidx.shape[0])
+
+    @property
+    def boff(self) -> np.ndarray:
+        return np.concatenate([[0], np.cumsum(self.bsize.astype(np.int64))])
+
+    @property
+    def ndof(self) -> int:
+        return int(self.bsize.sum())
+
+
+def vb_block_sizes(n: int, dim: int, p_interior: int, p_boundary: int) -> np.ndarray:
+    """Local space sizes C(p + d, d) per patch of an n^dim grid: polynomial
+    degree p_boundary on the patches that touch the boundary (any coordinate 0
+    or n - 1), p_interior elsewhere; x fastest."""
+    coords = np.indices((n,) * dim).reshape(dim, -1)[::-1]
+    boundary = np.any((coords == 0) | (coords == n - 1), axis=0)
+    return np.where(boundary, pum_block_size(p_boundary, dim), pum_block_size(p_interior, dim)).astype(np.int32)
+
+
+def make_vb_problem(n: int, dim: int, power: int, p_interior: int = 2, p_boundary: int = 3,
+                    seed: int = 0) -> VarProblem:
+    """A = B^T (D (x) I_M) B on an n^dim patch grid with block sizes m_i from
+    vb_block_sizes, M = max m_i: B is block diagonal with the M x m_i blocks
+    B_i = Q_i[:, :m_i] diag(exp(u_i)), Q_i Haar-orthogonal M x M and
+    u_i ~ U[-1, 1]^{m_i}, so block (i, j) is D_ij B_i^T B_j (m_i x m_j) and
+    A_ii = D_ii diag(exp(2 u_i)). A is SPD because B has full column rank.
+    Streams as in make_problem: SeedSequence(seed).spawn(4) -> (Q, u, RHS,
+    Lanczos)."""
+    dmat = stencil_matrix(n, dim, power)
+    nb = dmat.shape[0]
+    m = vb_block_sizes(n, dim, p_interior, p_boundary)
+    big = int(m.max())
+    streams = _streams(seed)
+    q = _haar_orthogonal(streams[STREAM_Q], nb, big)
+    u = streams[STREAM_U].uniform(-1.0, 1.0, size=(nb, big))
+    rowptr = dmat.indptr.astype(np.int64)
+    colidx = dmat.indices.astype(np.int32)
+    rows = np.repeat(np.arange(nb, dtype=np.int64), np.diff(rowptr))
+    sizes = m[rows].astype(np.int64) * m[colidx]
+    voff = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    vals = np.empty(int(voff[-1]))
+    bfull = q * np.exp(u)[:, None, :]          # Q_i diag(exp u_i); B_i is its first m_i columns
+    mi, mj = m[rows], m[colidx]
+    for a in np.unique(m):
+        for c in np.unique(m):
+            sel = np.nonzero((mi == a) & (mj == c))[0]
+            for s0 in range(0, len(sel), 1 << 16):
+                es = sel[s0:s0 + (1 << 16)]
+                blk = np.swapaxes(bfull[rows[es], :, :a], 1, 2) @ bfull[colidx[es], :, :c]
+                blk *= dmat.data[es, None, None]
+                idx = voff[es][:, None] + np.arange(a * c)[None, :]
+                vals[idx] = blk.reshape(len(es), -1)
+    return VarProblem(n=n, dim=dim, power=power, seed=seed, bsize=m, rowptr=rowptr, colidx=colidx, vals=vals,
+                      voff=voff, dstencil=dmat)
+
+
 def pum_block_size(p: int, dim: int) -> int:
     """dim V_i = C(p + d, d) for local polynomials of degree p."""
     return comb(p + dim, dim)
