@@ -217,7 +217,8 @@ def c2_leg(args, chf, torch, dev):
                         f"{L}-level Galerkin V({k},{k}), cubic patch transfer, adaptive t_max={cfg.tmax}, "
                         f"PCG rtol {cfg.rtol:g}"), "nnzb_A": nnzb}
     x64 = None
-    for name, dt in [("fp64", chf.F64), ("mixed_f32", chf.F32), ("mixed_bf16g", chf.BF16)]:
+    for name, dt in [("fp64", chf.F64), ("mixed_f32", chf.F32), ("mixed_bf16g", chf.BF16),
+                     ("fp64_bf16g", chf.F64_BF16G)]:
         rec = {}
         H = chf.levels_create(A)
         torch.cuda.synchronize()
@@ -235,12 +236,16 @@ def c2_leg(args, chf, torch, dev):
             Al, _, _ = chf.levels_get(H, l)
             nb_l, _, nz_l = Al.info()
             rec["blocks_per_row_A"].append(round(nz_l / nb_l, 1))
-        flex = dt != chf.F64
+        flex = dt in (chf.F32, chf.BF16)
+        # the FP32-A cycle stalls near a recursive 2e-9 on this operator: those
+        # forms are run to 1e-8 (the biharmonic workload's target)
+        rtol = 1e-8 if flex else cfg.rtol
+        rec["rtol"] = rtol
         xs = torch.zeros(N, dtype=torch.float64, device=dev)
-        chf.pcg_solve(H, bd, xs, rtol=cfg.rtol, maxit=400, flexible=flex, raise_on_noconv=False)   # warm-up
+        chf.pcg_solve(H, bd, xs, rtol=rtol, maxit=400, flexible=flex, raise_on_noconv=False)   # warm-up
         torch.cuda.synchronize()
         t = time.perf_counter()
-        it, hist, tr, rc = chf.pcg_solve(H, bd, xs, rtol=cfg.rtol, maxit=400, flexible=flex, raise_on_noconv=False)
+        it, hist, tr, rc = chf.pcg_solve(H, bd, xs, rtol=rtol, maxit=400, flexible=flex, raise_on_noconv=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t
         rec.update({"iterations": it, "time_ms": round(1e3 * el, 2), "ms_per_iteration": round(1e3 * el / max(it, 1), 3),
@@ -251,7 +256,7 @@ def c2_leg(args, chf, torch, dev):
         beta0 = chf.levels_get_beta(H, 0)
         _, pcol = chf.pattern_export(P0)
         nnzg = len(pcol)
-        vt = torch.float64 if dt == chf.F64 else torch.float32
+        vt = torch.float64 if dt in (chf.F64, chf.F64_BF16G) else torch.float32
         bb_ = bd.to(vt)
         x = torch.zeros(N, dtype=vt, device=dev)
         work = torch.zeros(3 * N, dtype=vt, device=dev)
@@ -264,7 +269,7 @@ def c2_leg(args, chf, torch, dev):
             b_.record(stream)
         torch.cuda.synchronize()
         ms = float(np.median([a_.elapsed_time(b_) for a_, b_ in evs]))
-        sa, sv = (8, 8) if dt == chf.F64 else (4, 4)
+        sa, sv = (8, 8) if dt in (chf.F64, chf.F64_BF16G) else (4, 4)
         sg = 8 if dt == chf.F64 else (4 if dt == chf.F32 else 2)
         b_app = k * (nnzb * (b * b * sa + 4) + 2 * nnzg * (b * b * sg + 4) + 10 * N * sv)
         rec["smoother"] = {"median_ms_per_application_20_calls": round(ms, 4), "algorithmic_bytes_per_application": b_app,
@@ -283,8 +288,7 @@ def c2_leg(args, chf, torch, dev):
         log(f"c2 {name}: {rec}")
         H.destroy()
         del work, x
-    out["mixed_f32_over_fp64_time"] = round(out["mixed_f32"]["time_ms"] / out["fp64"]["time_ms"], 4)
-    out["mixed_bf16g_over_fp64_time"] = round(out["mixed_bf16g"]["time_ms"] / out["fp64"]["time_ms"], 4)
+    out["fp64_bf16g_over_fp64_time"] = round(out["fp64_bf16g"]["time_ms"] / out["fp64"]["time_ms"], 4)
     return out
 
 
@@ -681,7 +685,7 @@ def main():
     if not args.no_pcg:
         res = {}
         for name, dt, flex, Hh in [("fp64", chf.F64, False, H), ("mixed_f32", chf.F32, True, None),
-                                   ("mixed_bf16g", chf.BF16, True, None)]:
+                                   ("mixed_bf16g", chf.BF16, True, None), ("fp64_bf16g", chf.F64_BF16G, False, None)]:
             setup = None
             if Hh is None:
                 log(f"set-up {name} hierarchy")
@@ -701,12 +705,14 @@ def main():
                 res[name]["setup"] = {kk: round(v, 2) for kk, v in setup.items()}
             if dt != chf.F64:
                 # one level-0 smoother application with this hierarchy's operators
-                # (A in FP32; G in FP32 or BF16; FP32 vectors), timed like the FP64 one
+                # (A in FP32, G in FP32 or BF16, FP32 vectors; or FP64 A and vectors
+                # with BF16 G), timed like the FP64 one
                 A0m, G0m, _ = chf.levels_get(Hh, 0)
                 beta_m = chf.levels_get_beta(Hh, 0)
-                b32 = bd.float()
-                x32 = torch.zeros(N, dtype=torch.float32, device=dev)
-                w32 = torch.zeros(3 * N, dtype=torch.float32, device=dev)
+                vt = torch.float64 if dt == chf.F64_BF16G else torch.float32
+                b32 = bd.to(vt)
+                x32 = torch.zeros(N, dtype=vt, device=dev)
+                w32 = torch.zeros(3 * N, dtype=vt, device=dev)
                 for _ in range(args.warmup):
                     chf.cheb4_smooth(A0m, G0m, beta_m, k, b32, x32, work=w32, dtype=dt)
                 torch.cuda.synchronize()
@@ -717,7 +723,8 @@ def main():
                 torch.cuda.synchronize()
                 ms_m = e0.elapsed_time(e1) / args.steps
                 sg = 4 if dt == chf.F32 else 2
-                b_m = k * (nnzb * (b * b * 4 + 4) + 2 * nnzg * (b * b * sg + 4) + 10 * N * 4)
+                sa = sv = 8 if dt == chf.F64_BF16G else 4
+                b_m = k * (nnzb * (b * b * sa + 4) + 2 * nnzg * (b * b * sg + 4) + 10 * N * sv)
                 res[name]["smoother"] = {"ms_per_application": round(ms_m, 5), "algorithmic_bytes_per_application": b_m,
                                          "achieved_GBs": round(b_m / (ms_m * 1e-3) / 1e9, 1),
                                          "hbm_frac": round(b_m / (ms_m * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -726,11 +733,12 @@ def main():
                 Hh.destroy()
         if n == 512 and L == 6 and k == 4 and args.tmax == 8 and os.path.exists(GOLDEN_C1):
             gold = json.load(open(GOLDEN_C1))["dirichlet"]["pcg"]
-            for name in ("fp64", "mixed_f32", "mixed_bf16g"):
+            for name in ("fp64", "mixed_f32", "mixed_bf16g", "fp64_bf16g"):
                 if name in gold:
                     res[name]["oracle_iterations"] = gold[name]["iterations"]
         res["mixed_f32_over_fp64_time"] = round(res["mixed_f32"]["time_ms"] / res["fp64"]["time_ms"], 4)
         res["mixed_bf16g_over_fp64_time"] = round(res["mixed_bf16g"]["time_ms"] / res["fp64"]["time_ms"], 4)
+        res["fp64_bf16g_over_fp64_time"] = round(res["fp64_bf16g"]["time_ms"] / res["fp64"]["time_ms"], 4)
         out["pcg"] = res
 
     if not args.no_comparators:

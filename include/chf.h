@@ -53,7 +53,14 @@ typedef enum {
     CHF_EBREAKDOWN = -6   /* PCG breakdown: p^T A p <= 0 or r^T z <= 0 */
 } chf_status;
 
-typedef enum { CHF_F64 = 0, CHF_F32 = 1, CHF_BF16 = 2 } chf_dtype;
+/* Storage and working precision. CHF_F64, CHF_F32, CHF_BF16 name a storage
+ * type (and, as a working mode: FP64 throughout; FP32 A with FP32 vectors and
+ * G in FP32 or BF16). CHF_F64_BF16G is a working mode only: A, vectors and
+ * arithmetic in FP64 with the factor G read from its BF16 copy (a factor set
+ * up with g_store = CHF_BF16 keeps both copies). It is accepted by the
+ * smoothers, chf_fsai_apply, chf_lmax_lanczos and chf_level_opts.dtype, where
+ * it builds every level's G with BF16 storage. */
+typedef enum { CHF_F64 = 0, CHF_F32 = 1, CHF_BF16 = 2, CHF_F64_BF16G = 3 } chf_dtype;
 typedef enum { CHF_SMOOTH_CHEB4 = 0, CHF_SMOOTH_CHEB1 = 1, CHF_SMOOTH_RICHARDSON = 2 } chf_smoother;
 typedef enum { CHF_CYCLE_VKK = 0, CHF_CYCLE_V2K0 = 1 } chf_cycle;
 
@@ -225,7 +232,8 @@ typedef struct {
     double tau;          /* adaptive threshold (1.0 in the paper) */
     int lanczos_iters;   /* 100 in the paper */
     double safety;       /* 1.01 in the paper */
-    chf_dtype dtype;     /* F64: plain; F32: A_l, G_l FP32; BF16: A_l FP32, G_l BF16 */
+    chf_dtype dtype;     /* F64: plain; F32: A_l, G_l FP32; BF16: A_l FP32, G_l BF16 (FP32 vectors);
+                            F64_BF16G: A_l and vectors FP64, G_l BF16 */
 } chf_level_opts;
 
 /* Empty hierarchy whose finest operator is A0 (borrowed: A0 must outlive L). */

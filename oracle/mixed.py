@@ -14,7 +14,11 @@ by the Lanczos process of Sec. 5 on the rounded operators, evaluated in FP64.
 The outer solver is FP64 PCG in its flexible (Polak-Ribiere) form, since the
 rounded cycle is not exactly symmetric.
 
-Parity of the mixed form is unpinned beyond the roundings themselves: its
+A second form keeps A, the vectors and the arithmetic in FP64 and rounds only
+G to BF16 (bf16g_levels): it halves the bytes of the two factor products per
+smoothing step while the cycle sees the exact operator.
+
+Parity of the mixed forms is unpinned beyond the roundings themselves: their
 error against the FP64 oracle is reported, not derived.
 """
 from __future__ import annotations
@@ -96,6 +100,24 @@ def mixed_levels(levels, g_store: str, starts, iters: int = 100, safety: float =
                                             format="csr"), dtype=np.float32)
         out.append(MixedLevel(a=_bsr32(a, ar), g=g32, gt=g32.T.tobsr(blocksize=(a.b, a.b)), ps=ps, t=t,
                               beta=beta))
+    return out
+
+
+def bf16g_levels(levels, starts, iters: int = 100, safety: float = 1.01):
+    """The FP64 hierarchy with every smoothed level's G replaced by its BF16
+    rounding (A, vectors and arithmetic stay FP64) and beta_l recomputed by
+    Lanczos on the rounded factor; the result is used with the plain FP64
+    cycle of oracle.multilevel."""
+    from .multilevel import Level
+    out = []
+    for l, lev in enumerate(levels):
+        if lev.g is None:
+            out.append(lev)
+            continue
+        g = Bsr(lev.g.rowptr, lev.g.colidx, round_bf16(lev.g.vals), lev.g.b)
+        new = Level(a=lev.a, g=g, p_s=lev.p_s, basis=lev.basis).finish()
+        new.beta, _ = lanczos.lmax(new.apply_b, np.asarray(starts[l]), iters, safety)
+        out.append(new)
     return out
 
 

@@ -7,7 +7,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "F64", "F32", "BF16", "NFEAT", "NPARAM", "SMOOTH_CHEB4", "SMOOTH_CHEB1", "SMOOTH_RICHARDSON", "CYCLE_VKK", "CYCLE_V2K0",
+    "F64", "F32", "BF16", "F64_BF16G", "NFEAT", "NPARAM", "SMOOTH_CHEB4", "SMOOTH_CHEB1", "SMOOTH_RICHARDSON", "CYCLE_VKK", "CYCLE_V2K0",
     "ChfError", "lib", "lib_path", "version", "current_stream",
     "Bsr", "Pattern", "Fsai", "Levels", "Mlp", "LevelOpts",
     "bsr_create", "bsr_export", "bsr_spmv", "vbsr_create", "vbsr_info",
@@ -23,7 +23,7 @@ __all__ = [
     "EXPORTED",
 ]
 
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, F64_BF16G = 0, 1, 2, 3
 SMOOTH_CHEB4, SMOOTH_CHEB1, SMOOTH_RICHARDSON = 0, 1, 2
 CYCLE_VKK, CYCLE_V2K0 = 0, 1
 CHF_ENOCONV = -5

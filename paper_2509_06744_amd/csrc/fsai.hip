@@ -815,8 +815,8 @@ void lanczos_impl(chf_bsr A, const chf_fsai_s& G, chf_dtype dt, int iters, const
     CHF_CHECK(iters >= 1, CHF_EINVAL, "iters must be >= 1");
     CHF_CHECK(!A->vb || dt == CHF_F64, CHF_EINVAL, "variable block sizes: FP64 only");
     const int m = (int)std::min<int64_t>(iters, n);
-    const Sell& sa = A->sell(dt == CHF_F64 ? CHF_F64 : CHF_F32, s);
-    const FactorOps fo = factor_ops(G, dt);
+    const Sell& sa = A->sell(mode_vec(dt), s);
+    const FactorOps fo = factor_ops(G, mode_g(dt));
     DevBuf<double> vbuf(3 * n), w(n), t1(n), scal(2 * m + 4), part(RED_BLOCKS);
     double* va = vbuf.p;
     double* vb = vbuf.p + n;
@@ -1004,9 +1004,10 @@ extern "C" int chf_fsai_apply(chf_fsai G, chf_dtype dtype, const void* r, void* 
                               hipStream_t stream) {
     return guarded([&] {
         CHF_CHECK(G && r && z && work, CHF_EINVAL, "NULL argument");
-        CHF_CHECK(dtype == CHF_F64 || G->store == dtype || (dtype == CHF_F32 && G->store == CHF_BF16),
+        CHF_CHECK(dtype == CHF_F64 || G->store == dtype || (dtype == CHF_F32 && G->store == CHF_BF16) ||
+                      (dtype == CHF_F64_BF16G && G->store == CHF_BF16),
                   CHF_EINVAL, "dtype does not match the factor's storage");
-        chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
+        chf_dtype vec = mode_vec(dtype);
         chf_dtype use = dtype == CHF_F64 ? CHF_F64 : G->store;
         const FactorOps fo = factor_ops(*G, use);
         sell_spmv(*fo.g, vec, r, work, nullptr, EPI_AX, nullptr, nullptr, 0, 0, stream);
@@ -1023,7 +1024,9 @@ extern "C" int chf_lmax_lanczos(chf_bsr A, chf_fsai G, chf_dtype dtype, int iter
     return guarded([&] {
         CHF_CHECK(A && G && v0, CHF_EINVAL, "NULL argument");
         CHF_CHECK(A->nb == G->nb && A->b == G->b, CHF_EINVAL, "A and G sizes differ");
-        CHF_CHECK(dtype == CHF_F64 || dtype == G->store, CHF_EINVAL, "dtype does not match the factor's storage");
+        CHF_CHECK(dtype == CHF_F64 || dtype == G->store || (dtype == CHF_F64_BF16G && G->store == CHF_BF16),
+                  CHF_EINVAL, "dtype does not match the factor's storage");
+        CHF_CHECK(A->vb == G->base().vb, CHF_EINVAL, "A and G block structures differ");
         lanczos_impl(A, *G, dtype, iters, v0, safety, beta, theta, stream);
     });
 }

@@ -233,6 +233,9 @@ inline FactorOps factor_ops(const chf_fsai_s& G, chf_dtype t) {
 constexpr int MLP_NIN = 6;
 // Block-FSAI factor of a variable-block matrix (vbsr.hip).
 chf_fsai_s* vfsai_setup_impl(chf_bsr A, const chf_pattern_s& P, int64_t* bad_row, hipStream_t s);
+// Working mode -> (vector dtype, storage dtype of the factor's layouts used).
+inline chf_dtype mode_vec(chf_dtype mode) { return (mode == CHF_F64 || mode == CHF_F64_BF16G) ? CHF_F64 : CHF_F32; }
+inline chf_dtype mode_g(chf_dtype mode) { return mode == CHF_F64_BF16G ? CHF_BF16 : mode; }
 // Deterministic FP64 reductions (fixed grid, fixed tree).
 constexpr int RED_BLOCKS = 512;
 // out[0] = sum x_i y_i over n doubles/floats (vec dtype), accumulated in FP64.

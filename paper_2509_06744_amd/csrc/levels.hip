@@ -596,7 +596,7 @@ static void prolong_add(chf_levels_s& H, int l, const void* xc, void* x, hipStre
 static void smooth_level(chf_levels_s& H, int l, int degree, const void* b, void* x, bool x_is_zero, hipStream_t s) {
     chf_level_s& L = H.lev[l];
     const Sell& A = level_A(H, l, s);
-    const chf_dtype gdt = H.vec == CHF_F64 ? CHF_F64 : L.G->store;
+    const chf_dtype gdt = H.vec == CHF_F64 ? mode_g(H.opts.dtype) : L.G->store;
     const FactorOps G = factor_ops(*L.G, gdt);
     switch (H.smoother) {
         case CHF_SMOOTH_CHEB1:
@@ -801,11 +801,13 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
         CHF_CHECK(opts->degree >= 1, CHF_EINVAL, "degree must be >= 1");
         CHF_CHECK(opts->pattern >= 0 && opts->pattern <= 2, CHF_EINVAL, "bad pattern mode");
         CHF_CHECK(!H->nest || opts->pattern == 1, CHF_EINVAL, "nesting needs the adaptive pattern (pattern = 1)");
-        CHF_CHECK(opts->dtype == CHF_F64 || opts->dtype == CHF_F32 || opts->dtype == CHF_BF16, CHF_EINVAL,
+        CHF_CHECK(opts->dtype == CHF_F64 || opts->dtype == CHF_F32 || opts->dtype == CHF_BF16 ||
+                      opts->dtype == CHF_F64_BF16G, CHF_EINVAL,
                   "bad dtype");
         if (bad_row) *bad_row = -1;
         H->opts = *opts;
-        H->vec = opts->dtype == CHF_F64 ? CHF_F64 : CHF_F32;
+        H->vec = mode_vec(opts->dtype);
+        const chf_dtype gstore = opts->dtype == CHF_F64_BF16G ? CHF_BF16 : opts->dtype;   // G's storage
         hipStream_t s = 0;
         const int nl = (int)H->lev.size();
         // pattern and factor of level l on stream st
@@ -832,10 +834,10 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
             if (H->nest) {
                 // outer factor for A_l, inner factor for G0 A_l G0^T with
                 // Algorithm 1's pattern (same t_max and tau)
-                L.G0 = fsai_setup_impl(L.A, *L.P, opts->dtype, br, st);
+                L.G0 = fsai_setup_impl(L.A, *L.P, gstore, br, st);
                 std::unique_ptr<chf_bsr_s> A1(bsr_triple_impl(L.A, *L.G0, st));
                 L.P1 = adaptive_pattern_impl(A1.get(), nullptr, opts->tmax, opts->tau, st);
-                L.G1 = fsai_setup_impl(A1.get(), *L.P1, opts->dtype, br, st);
+                L.G1 = fsai_setup_impl(A1.get(), *L.P1, gstore, br, st);
                 L.G = new chf_fsai_s;
                 L.G->nb = L.G0->nb;
                 L.G->b = L.G0->b;
@@ -843,7 +845,7 @@ extern "C" int chf_levels_setup(chf_levels H, const chf_level_opts* opts, const 
                 L.G->nest_outer = L.G0;
                 L.G->nest_inner = L.G1;
             } else {
-                L.G = fsai_setup_impl(L.A, *L.P, opts->dtype, br, st);
+                L.G = fsai_setup_impl(L.A, *L.P, gstore, br, st);
             }
         };
         // the coarsest level's dense factorisation; a non-SPD operator reports -2

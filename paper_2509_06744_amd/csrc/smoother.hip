@@ -146,11 +146,11 @@ int with_operands(chf_bsr A, chf_fsai G, chf_dtype dtype, const void* b, void* x
     return guarded([&] {
         CHF_CHECK(A && G && b && x && work, CHF_EINVAL, "NULL argument");
         CHF_CHECK(A->nb == G->nb && A->b == G->b && A->vb == G->base().vb, CHF_EINVAL, "A and G sizes differ");
-        CHF_CHECK(dtype == CHF_F64 || dtype == G->store, CHF_EINVAL,
-                  "dtype must be F64 or the factor's storage dtype");
-        chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
+        CHF_CHECK(dtype == CHF_F64 || dtype == G->store || (dtype == CHF_F64_BF16G && G->store == CHF_BF16),
+                  CHF_EINVAL, "dtype must be F64, the factor's storage dtype, or F64_BF16G for a BF16 factor");
+        const chf_dtype vec = mode_vec(dtype);
         const Sell& sa = A->sell(vec, stream);
-        f(sa, factor_ops(*G, dtype), vec);
+        f(sa, factor_ops(*G, mode_g(dtype)), vec);
     });
 }
 }  // namespace
@@ -189,9 +189,9 @@ extern "C" int chf_cheb4_smooth_noalloc(chf_bsr A, chf_fsai G, chf_dtype dtype, 
     return guarded([&] {
         CHF_CHECK(A && G && b && x, CHF_EINVAL, "NULL argument");
         CHF_CHECK(A->nb == G->nb && A->b == G->b && A->vb == G->base().vb, CHF_EINVAL, "A and G sizes differ");
-        CHF_CHECK(dtype == CHF_F64 || dtype == G->store, CHF_EINVAL,
-                  "dtype must be F64 or the factor's storage dtype");
-        const chf_dtype vec = dtype == CHF_F64 ? CHF_F64 : CHF_F32;
+        CHF_CHECK(dtype == CHF_F64 || dtype == G->store || (dtype == CHF_F64_BF16G && G->store == CHF_BF16),
+                  CHF_EINVAL, "dtype must be F64, the factor's storage dtype, or F64_BF16G for a BF16 factor");
+        const chf_dtype vec = mode_vec(dtype);
         const int64_t n = A->ndof;
         CHF_CHECK((size_t)n * 3 * vec_size(vec) <= kNoallocScratchBytes, CHF_EINVAL,
                   "chf_cheb4_smooth_noalloc: 3 vectors of " + std::to_string(n) +
@@ -202,7 +202,8 @@ extern "C" int chf_cheb4_smooth_noalloc(chf_bsr A, chf_fsai G, chf_dtype dtype, 
                   "chf_cheb4_smooth_noalloc: the FP32 layout of A does not exist yet (make one FP32 call of "
                   "chf_cheb4_smooth or chf_bsr_spmv first)");
         const Sell& sa = vec == CHF_F64 ? A->sell64 : A->sell32;
-        cheb4_impl(sa, factor_ops(*G, dtype), vec, beta, degree, b, x, x_is_zero != 0, noalloc_scratch(), stream);
+        cheb4_impl(sa, factor_ops(*G, mode_g(dtype)), vec, beta, degree, b, x, x_is_zero != 0, noalloc_scratch(),
+                   stream);
     });
 }
 

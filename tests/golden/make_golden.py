@@ -14,9 +14,10 @@ PCG to a recursive relative residual of 1e-10.
 
 Both: adaptive block-FSAI on every smoothed level (Algorithm 1, P0 =
 diagonal, tau = 1, t_max = 8), Lanczos bounds (Sec. 5: 100 steps, x 1.01),
-V(4,4) with fourth-kind Chebyshev smoothing, PCG from x = 0 in three forms:
-FP64 (Fletcher-Reeves), and the mixed forms with A, G in FP32 or A in FP32
-and G in BF16 (flexible PCG around the FP32 cycle).
+V(4,4) with fourth-kind Chebyshev smoothing, PCG from x = 0 in four forms:
+FP64 (Fletcher-Reeves), the mixed forms with A, G in FP32 or A in FP32 and G
+in BF16 (flexible PCG around the FP32 cycle), and FP64 with G rounded to BF16
+(Fletcher-Reeves).
 
 Only oracle/ and the input generator are called. Block rows are independent
 in Algorithm 1 and in the factor of Def. 2.2, so their rows are computed by a
@@ -145,6 +146,10 @@ def _pcg_worker(form):
     if form == "fp64":
         return form, run_pcg(form, levels[0].apply_a, lambda r: multilevel.vcycle(levels, 0, r, k), bvec, False,
                              rtol), None
+    if form == "fp64_bf16g":
+        lb = mixed.bf16g_levels(levels, starts)
+        return form, run_pcg(form, levels[0].apply_a, lambda r: multilevel.vcycle(lb, 0, r, k), bvec, False,
+                             rtol), [m.beta for m in lb[:-1]]
     ml = mixed.mixed_levels(levels, "f32" if form == "mixed_f32" else "bf16", starts)
     betas = [m.beta for m in ml[:-1]]
     return form, run_pcg(form, levels[0].apply_a, mixed.precond_mixed(ml, k), bvec, True, rtol), betas
@@ -179,8 +184,8 @@ def main():
            "levels": info, "pcg": {}}
     global _PCG
     _PCG = (levels, starts, bvec, k, rtol)   # forked workers read it; only the form name is sent
-    with ctx.Pool(3) as pool:
-        for form, rec, betas in pool.imap_unordered(_pcg_worker, ["fp64", "mixed_f32", "mixed_bf16g"]):
+    with ctx.Pool(4) as pool:
+        for form, rec, betas in pool.imap_unordered(_pcg_worker, ["fp64", "mixed_f32", "mixed_bf16g", "fp64_bf16g"]):
             if betas is not None:
                 rec["betas"] = betas
             out["pcg"][form] = rec

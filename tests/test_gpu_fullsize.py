@@ -105,7 +105,8 @@ def test_c1_pcg_fp64_and_mixed(chf, c1):
     p, a, _ = c1
     gold = _golden("c1_pcg_iterations.json")["dirichlet"]
     b_ = dev(rhs(0, p.ndof))
-    for dt, flex, name in [(0, False, "fp64"), (1, True, "mixed_f32"), (2, True, "mixed_bf16g")]:
+    for dt, flex, name in [(0, False, "fp64"), (1, True, "mixed_f32"), (2, True, "mixed_bf16g"),
+                           (3, False, "fp64_bf16g")]:
         A, L, _, _ = gpu_levels(p, 6, 4, 1, tmax=8, dtype=dt)
         if dt == 0:
             for rec in gold["levels"]:

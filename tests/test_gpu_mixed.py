@@ -99,7 +99,7 @@ def test_mixed_pcg_converges(chf, store):
     assert it <= it64 + (2 if store == 1 else 8)
 
 
-@pytest.mark.parametrize("dt,name", [(0, "fp64"), (1, "mixed_f32"), (2, "mixed_bf16g")])
+@pytest.mark.parametrize("dt,name", [(0, "fp64"), (1, "mixed_f32"), (2, "mixed_bf16g"), (3, "fp64_bf16g")])
 def test_triharmonic_pcg_matches_oracle_count(chf, dt, name):
     """b = 21 triharmonic-like (D = L^3) on 32x32 patches, 3 levels with the
     cubic patch transfer, adaptive t_max 8, V(4,4), PCG to a recursive 1e-10:
@@ -115,7 +115,7 @@ def test_triharmonic_pcg_matches_oracle_count(chf, dt, name):
     b_ = rhs(0, p.ndof)
     A, L, _, _ = gpu_levels(p, 3, 4, 1, tmax=8, dtype=dt, order=4)
     x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
-    it, hist, tr, _ = chf.pcg_solve(L, dev(b_), x, rtol=1e-10, maxit=300, flexible=dt != 0)
+    it, hist, tr, _ = chf.pcg_solve(L, dev(b_), x, rtol=1e-10, maxit=300, flexible=dt in (1, 2))
     print(f"triharmonic {name}: {it} iterations (oracle {gold['iterations']}), true relres {tr:.2e} "
           f"(oracle {gold['true_relres']:.2e})")
     assert hist[-1] <= 1e-10
@@ -145,3 +145,33 @@ def test_b21_rounded_products(chf, store):
     w = torch.zeros(p.ndof, dtype=torch.float32, device="cuda")
     chf.fsai_apply(G, dev(x, torch.float32), z, w, dtype=store)
     assert rel_err(host(z), gr.T @ (gr @ round_f32(x))) < 1e-5
+
+
+@pytest.mark.parametrize("n,b,pw,x_is_zero", [(24, 10, 2, True), (24, 10, 2, False), (16, 21, 3, True)])
+def test_fp64_bf16g_smoother_matches_oracle(chf, n, b, pw, x_is_zero):
+    """FP64 A, vectors and arithmetic with G read from its BF16 copy: the
+    oracle runs the same FP64 algorithm on the BF16-rounded G, so the
+    application matches it to the FP64 bar (1e-12); the Lanczos bound on the
+    rounded factor matches too."""
+    import torch
+    p = make_problem(n, 2, b, pw, seed=0)
+    a = from_problem(p)
+    prow, pcol = fsai.pattern_lower(a)
+    og = fsai.fsai(a, prow, pcol)
+    asp = a.scipy()
+    gr = Bsr(og.rowptr, og.colidx, round_bf16(og.vals), b).scipy()
+    grt = gr.T.tocsr()
+    v0 = lanczos_starts(0, [p.ndof])[0]
+    beta, theta = lanczos.lmax(lambda v: gr @ (asp @ (grt @ v)), v0)
+    b_ = rhs(0, p.ndof)
+    x0 = np.random.default_rng(2).standard_normal(p.ndof)
+    want = chebyshev.cheb4(lambda v: asp @ v, lambda v: grt @ (gr @ v), b_, None if x_is_zero else x0, beta, 4,
+                           x_is_zero=x_is_zero)
+    A = upload(p)
+    G = chf.fsai_setup(A, chf.pattern_lower(A), g_store=chf.BF16)
+    gb, gt = chf.lmax_lanczos(A, G, dev(v0), dtype=chf.F64_BF16G)
+    assert abs(gt - theta) < 1e-9 * theta
+    x = torch.zeros(p.ndof, dtype=torch.float64, device="cuda") if x_is_zero else dev(x0)
+    work = torch.zeros(3 * p.ndof, dtype=torch.float64, device="cuda")
+    chf.cheb4_smooth(A, G, beta, 4, dev(b_), x, x_is_zero=x_is_zero, work=work, dtype=chf.F64_BF16G)
+    assert rel_err(host(x), want) < 1e-12
