@@ -460,8 +460,482 @@ __device__ void fsai_row_tiled(int64_t k, int b, const int* __restrict__ a_rowpt
     __syncthreads();
 }
 
+// ---------------------------------------------------- register-resident --
+// Rows with 16 < n <= 240 (at most 15 x 15 tiles) can keep the whole upper
+// triangle of the padded local matrix in the registers of one workgroup of 8
+// wavefronts (one workgroup per CU, 15 tiles of 8 registers per lane each),
+// so nothing but A, the block map and G crosses the memory hierarchy. The
+// padding rows come first here (identity, decoupled from the rest), which
+// puts block row k in the last b rows of the last tile row.
+//
+// The factorisation is block LDL^T over 16 x 16 tiles, U_ab = Kpad tile (a, b)
+// for a <= b, D_c the diagonal tile after the updates of the steps before c:
+//   step c:  Dinv = D_c^{-1}, W_cb = Dinv U_cb (b > c),
+//            U_ab -= U_ca^T W_cb (c < a <= b).
+// With Lt the block unit lower factor (Lt_bc = W_cb^T) and R_c = chol(D_c),
+// the Cholesky factor is L = Lt blockdiag(R_c); the last tile row of L^{-1}
+// is X V with X = R_{T-1}^{-1} and V the last tile row of Lt^{-1}:
+//   V_{T-1} = I,  V_a = -sum_{b > a} V_b W_ab^T,
+// and G_k is the last b rows of X V. The sequential work per step is one
+// 16 x 16 inverse on one wavefront, done by block sweeps on MFMA; the other
+// wavefronts update their tiles meanwhile.
+//
+// MFMA operand layouts (v_mfma_f64_16x16x4f64, lane l, g = l / 16, j = l % 16):
+// step q reads A[j][4q + g] and B[4q + g][j]; accumulator element rr holds
+// row 4 rr + g, column j. A tile held in accumulator layout therefore serves
+// directly as B, and as A for its transpose.
+constexpr int RR_WAVES = 8;
+constexpr int RR_NT = 64 * RR_WAVES;
+constexpr int RR_TMAX = 15;
+constexpr int RR_MAXN = 16 * RR_TMAX;
+constexpr int RR_SLOTS = (RR_TMAX * (RR_TMAX + 1) / 2 + RR_WAVES - 1) / RR_WAVES;   // 15
+
+__device__ __forceinline__ double sel4(int i, double a0, double a1, double a2, double a3) {
+    double r = a3;
+    r = i == 2 ? a2 : r;
+    r = i == 1 ? a1 : r;
+    r = i == 0 ? a0 : r;
+    return r;
+}
+
+// 1 / x to double precision, likewise: y <- y + y (1 - x y).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
+// 1 / sqrt(x) to double precision: the hardware estimate refined by two
+// Newton steps y <- y + y (1 - x y^2) / 2 (each at least doubles the correct
+// bits), in place of a square root and a division on the sequential path.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// One block step of a 4 x 4 SPD pivot P (the same on every lane; lower
+// triangle used), by P = L D L^T with L unit lower: X = D^{-1/2} L^{-1} is
+// chol(P)^{-1} and P^{-1} = X^T X. Returned as the entries this lane needs
+// for the padded 16 x 4 MFMA operands, pin = P^{-1}[j][g] and xin = X[j][g]
+// (zero for j >= 4). False if a pivot is not positive and finite.
+__device__ __forceinline__ bool chol_inv4(const double (&P)[4][4], int g, int j, double& pin, double& xin) {
+    double L[4][4], e[4][4], sq[4];
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        // e[i][c] = L[i][c] d_c (the unscaled column), d_c = P_cc - sum_t L[c][t] e[c][t]
+        double d = P[c][c];
+#pragma unroll
+        for (int t = 0; t < c; ++t) d -= L[c][t] * e[c][t];
+        ok = ok && (d > 0.0) && isfinite(d);
+        sq[c] = rsqrt_nr(fmax(d, 1e-300));
+        const double r = sq[c] * sq[c];
+#pragma unroll
+        for (int i = c + 1; i < 4; ++i) {
+            double v = P[i][c];
+#pragma unroll
+            for (int t = 0; t < c; ++t) v -= L[i][t] * e[c][t];
+            e[i][c] = v;
+            L[i][c] = v * r;
+        }
+    }
+    // Y = L^{-1} (unit lower), X[i][c] = Y[i][c] / sqrt(d_i)
+    double Y[4][4], X[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Y[i][c] = c == i ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < i; ++c) {
+            double v = L[i][c];
+#pragma unroll
+            for (int t = c + 1; t < i; ++t) v += L[i][t] * Y[t][c];
+            Y[i][c] = -v;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) X[i][c] = Y[i][c] * sq[i];
+    }
+    // columns j and g of X on this lane; P^{-1}[j][g] = sum_t X[t][j] X[t][g]
+    double xj[4], xg[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        xj[t] = sel4(j, X[t][0], X[t][1], X[t][2], X[t][3]);
+        xg[t] = sel4(g, X[t][0], X[t][1], X[t][2], X[t][3]);
+    }
+    double pi = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) pi += xj[t] * xg[t];
+    pin = j < 4 ? pi : 0.0;
+    xin = j < 4 ? sel4(j, xg[0], xg[1], xg[2], xg[3]) : 0.0;
+    return ok;
+}
+
+// In place on an SPD tile M in accumulator layout (one wavefront), by 4 x 4
+// blocks p with pivot P (entry (i, c) of P sits in element p of lane
+// 16 i + 4 p + c):
+//  - chol = false: M <- M^{-1} by block sweeps. Sweeping p maps M_pp to
+//    -P^{-1}, M_pj to P^{-1} M_pj, M_ip to M_ip P^{-1} and M_ij to
+//    M_ij - M_ip P^{-1} M_pj. With a = M[:, p] - lam E_p (E_p the identity
+//    columns of p), M - a P^{-1} a^T gives all four at once up to scale:
+//    lam P^{-1} M_pj, lam M_ip P^{-1} and 2 lam I - lam^2 P^{-1}; so -2 lam
+//    on the diagonal of P and 1 / lam on the rows and columns of p finish the
+//    step. lam = trace(P) / 4 keeps the row and column terms free of the
+//    cancellation a unit shift suffers when P is far from the identity in
+//    scale. Sweeping every block leaves -M^{-1}.
+//  - chol = true: M <- chol(M)^{-1} (lower), by forward elimination of
+//    [M | I]: the rows below p take -= M[i, p] P^{-1} [M | Y][p, :], then
+//    Y[p, :] <- chol(P)^{-1} Y[p, :].
+// M stays symmetric in the part still read (all of it for the sweep, the
+// trailing part for the elimination), so column p of M is row p read across
+// lanes: element p of this lane's accumulator.
+template <bool chol>
+__device__ inline bool tile_inverse(v4d& m, int lane) {
+    const int g = lane >> 4, j = lane & 15;
+    v4d y = {0.0, 0.0, 0.0, 0.0};
+    if constexpr (chol) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[q] = (4 * q + g == j) ? 1.0 : 0.0;
+    }
+    bool ok = true;
+#pragma unroll
+    for (int blk = 0; blk < 4; ++blk) {
+        double P[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int c = 0; c <= i; ++c) P[i][c] = lane_bcast(m[blk], 16 * i + 4 * blk + c);
+        double pin, xin;
+        ok = chol_inv4(P, g, j, pin, xin) && ok;
+        const bool dg = j == 4 * blk + g;
+        const double lam = 0.25 * (P[0][0] + P[1][1] + P[2][2] + P[3][3]);
+        const double sw = m[blk] - (dg ? lam : 0.0);
+        const double av = chol ? (j >= 4 * blk + 4 ? m[blk] : 0.0) : sw;   // A: column p (rows i)
+        const double bv = chol ? m[blk] : sw;                               // B: row p
+        v4d t = {0.0, 0.0, 0.0, 0.0};
+        t = mfma16(pin, bv, t);   // rows 0..3: P^{-1} B
+        if constexpr (chol) {
+            v4d ty = {0.0, 0.0, 0.0, 0.0}, ts = ty;
+            ty = mfma16(pin, y[blk], ty);
+            ts = mfma16(xin, y[blk], ts);
+            y = mfma16(-av, ty[0], y);
+            y[blk] = ts[0];
+        }
+        m = mfma16(-av, t[0], m);
+        if constexpr (!chol) {
+            const double rl = rcp_nr(lam);
+            if (dg) m[blk] -= 2.0 * lam;
+            m[blk] *= rl;                         // rows of p
+            if (j >= 4 * blk && j < 4 * blk + 4) {   // columns of p
+#pragma unroll
+                for (int q = 0; q < 4; ++q) m[q] *= rl;
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) m[q] = chol ? y[q] : -m[q];
+    return ok;
+}
+
+// The slot word, opaque to the optimiser at each use: keeps the per-slot LDS
+// addresses from being hoisted out of the step loops (15 slots x 2 arrays of
+// live addresses would not fit beside the tiles). For the same reason the
+// slot loops below end each slot with a scheduling barrier: the operands of
+// all slots loaded together would not fit either.
+__device__ __forceinline__ int slot_word(int v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+// Persistent: one workgroup per CU pops rows of order[0 .. nrows). The order
+// is cut into chunks of RR_CHUNK consecutive rows (neighbours in space, which
+// share most blocks of A), and chunk c goes to XCD c % nx (workgroups are
+// dealt to the XCDs in turn; nx = min(8, grid)), each XCD popping from its
+// own counter, so that a chunk's rows meet in one L2.
+// bmul = ceil(2^16 / b): x / b = (x * bmul) >> 16 for 0 <= x < 2^16 / b.
+constexpr int RR_CHUNK = 32;
+__global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const int64_t* __restrict__ order, int b,
+                                                         int bmul, const int* __restrict__ a_rowptr,
+                                                         const int* __restrict__ a_col,
+                                                         const double* __restrict__ a_vals,
+                                                         const int64_t* __restrict__ p_rowptr,
+                                                         const int* __restrict__ p_col, double* __restrict__ g_vals,
+                                                         int* xcd_counters, int* bad_row) {
+    __shared__ int idx[FSAI_MAXM * FSAI_MAXM];
+    __shared__ double pu[RR_TMAX * 256];   // U_c. of the panel row; S in the back-substitution
+    __shared__ double pw[RR_TMAX * 256];   // W_c. of the panel row
+    __shared__ double vv[RR_TMAX * 256];   // V, then X V
+    __shared__ double dinv[256];           // D_c^{-1}; X = R_{T-1}^{-1} at the end
+    __shared__ int sh_flag;
+    __shared__ int64_t sh_next;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, j = lane & 15;
+    const int nx = min((int)gridDim.x, 8), xcd = (int)blockIdx.x % nx;
+    for (;;) {
+        if (tid == 0) {
+            const int64_t i = atomicAdd(xcd_counters + xcd, 1);
+            const int64_t it = ((i / RR_CHUNK) * nx + xcd) * RR_CHUNK + i % RR_CHUNK;
+            sh_next = it < nrows ? it : -1;
+        }
+        __syncthreads();
+        const int64_t it = sh_next;
+        __syncthreads();
+        if (it < 0) break;
+        const int64_t k = order[it];
+        const int64_t p0 = p_rowptr[k];
+        const int m = __builtin_amdgcn_readfirstlane((int)(p_rowptr[k + 1] - p0));
+        const int n = m * b;
+        const int T = (n + 15) >> 4;
+        const int pad = 16 * T - n;
+        const int* cols = p_col + p0;
+        // block map idx[x m + y] = position of A[P_x, P_y] in A (or -1), all x, y
+        constexpr int IS = 4;
+        for (int t0 = tid; t0 < m * m; t0 += IS * RR_NT) {
+            int lo[IS], hi[IS], end[IS], want[IS];
+#pragma unroll
+            for (int s = 0; s < IS; ++s) {
+                const int t = t0 + s * RR_NT;
+                lo[s] = hi[s] = end[s] = 0;
+                want[s] = -1;
+                if (t < m * m) {
+                    const int x = t / m, y = t - x * m;
+                    const int row = cols[x];
+                    lo[s] = a_rowptr[row];
+                    hi[s] = end[s] = a_rowptr[row + 1];
+                    want[s] = cols[y];
+                }
+            }
+            for (;;) {
+                bool any = false;
+#pragma unroll
+                for (int s = 0; s < IS; ++s) {
+                    if (lo[s] < hi[s]) {
+                        any = true;
+                        const int mid = (lo[s] + hi[s]) >> 1;
+                        if (a_col[mid] < want[s]) lo[s] = mid + 1; else hi[s] = mid;
+                    }
+                }
+                if (!any) break;
+            }
+#pragma unroll
+            for (int s = 0; s < IS; ++s) {
+                const int t = t0 + s * RR_NT;
+                if (t < m * m) idx[t] = (want[s] >= 0 && lo[s] < end[s] && a_col[lo[s]] == want[s]) ? lo[s] : -1;
+            }
+        }
+        if (tid == 0) sh_flag = 1;
+        __syncthreads();
+        // Tiles of this wavefront. Diagonal tiles (a, a): wavefront a % 8,
+        // slot a / 8. The off-diagonal tiles, listed by tile row descending and
+        // column ascending, are dealt in turn starting at wavefront T % 8 (the
+        // first with one diagonal tile fewer), after the diagonal slots. Slot s
+        // holds tile (ab[s] >> 8, ab[s] & 255); ab[s] < 0 if unused.
+        int ab[RR_SLOTS];
+        {
+            const int ndiag = w < T ? (T - 1 - w) / 8 + 1 : 0;
+            const int rot = (w - (T & 7) + 8) & 7;
+            const int noff = T * (T - 1) / 2;
+#pragma unroll
+            for (int s = 0; s < RR_SLOTS; ++s) {
+                int v = -1;
+                if (s < ndiag) {
+                    v = (w + 8 * s) * 257;
+                } else {
+                    const int i = 8 * (s - ndiag) + rot;
+                    if (i < noff) {
+                        int r, o;
+                        tri_decode(i, r, o);
+                        v = (T - 2 - r) * 256 + (T - 1 - r + o);
+                    }
+                }
+                ab[s] = __builtin_amdgcn_readfirstlane(v);
+            }
+        }
+        // fill: element (4q + g, j) of U_ab is Kpad[16 a + 4q + g][16 b + j]
+        v4d t[RR_SLOTS];
+#pragma unroll
+        for (int s = 0; s < RR_SLOTS; ++s) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) t[s][q] = 0.0;
+            if (ab[s] >= 0) {
+                // every lane loads (padding lanes entry 0 of A), then selects
+                const int a = ab[s] >> 8, bt = ab[s] & 255;
+                const int pc = 16 * bt + j - pad;
+                const int pcc = max(pc, 0);
+                const int y = (pcc * bmul) >> 16, ry = pcc - y * b;
+                int e[4];
+                int64_t off[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int pr = 16 * a + 4 * q + g - pad;
+                    const int prc = max(pr, 0);
+                    const int x = (prc * bmul) >> 16, rx = prc - x * b;
+                    e[q] = (pr >= 0 && pc >= 0) ? idx[x * m + y] : -1;
+                    off[q] = e[q] >= 0 ? (int64_t)e[q] * b * b + rx * b + ry : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double v = a_vals[off[q]];
+                    const int pr = 16 * a + 4 * q + g - pad;
+                    t[s][q] = e[q] >= 0 ? v : ((pr == pc) ? 1.0 : 0.0);
+                }
+            }
+        }
+        // Steps c = -1 .. T - 2. Step c >= 0: panel row c (W_cb = Dinv U_cb to
+        // LDS with U_cb; the tile becomes W_cb^T for the back-substitution), then
+        // the trailing update. In every step the owner of the next diagonal
+        // tile dn = c + 1 updates it first and inverts it (the last one by its
+        // Cholesky factor) while the others update their tiles.
+        for (int c = -1; c + 1 < T; ++c) {
+            if (c >= 0) {
+                double xa[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xa[q] = dinv[64 * q + lane];   // Dinv[j][4q+g] (symmetric)
+#pragma unroll
+                for (int s = 0; s < RR_SLOTS; ++s) {
+                    const int v = slot_word(ab[s]);
+                    const int a = v >> 8, bt = v & 255;
+                    if (v >= 0 && a == c && bt > c) {
+                        // W = Dinv U and W^T = U^T Dinv: the same operands swapped
+                        v4d wv = {0.0, 0.0, 0.0, 0.0}, wt = wv;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            wv = mfma16(xa[q], t[s][q], wv);
+                            wt = mfma16(t[s][q], xa[q], wt);
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            pu[bt * 256 + 64 * q + lane] = t[s][q];
+                            pw[bt * 256 + 64 * q + lane] = wv[q];
+                        }
+                        t[s] = wt;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+            }
+            const int dn = c + 1;
+            if (w == (dn & 7)) {
+                v4d d = dn < 8 ? t[0] : t[1];
+                if (c >= 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        d = mfma16(-pu[dn * 256 + 64 * q + lane], pw[dn * 256 + 64 * q + lane], d);
+                }
+                bool ok;
+                if (dn + 1 < T) {
+                    // D^{-1}, stored symmetrised: its rounding asymmetry would
+                    // otherwise grow step by step through the Schur updates
+                    ok = tile_inverse<false>(d, lane);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dinv[64 * q + lane] = d[q];
+                    double dt[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dt[q] = dinv[j * 16 + 4 * q + g];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dinv[64 * q + lane] = 0.5 * (d[q] + dt[q]);
+                } else {
+                    ok = tile_inverse<true>(d, lane);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dinv[64 * q + lane] = d[q];
+                }
+                if (!ok && lane == 0) sh_flag = 0;
+            }
+            if (c >= 0) {
+#pragma unroll
+                for (int s = 0; s < RR_SLOTS; ++s) {
+                    const int v = slot_word(ab[s]);
+                    const int a = v >> 8, bt = v & 255;
+                    if (v >= 0 && a > c && !(a == dn && bt == dn)) {
+                        double pa[4], pb[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            pa[q] = pu[a * 256 + 64 * q + lane];    // U_ca^T[j][4q+g]
+                            pb[q] = pw[bt * 256 + 64 * q + lane];   // W_cb[4q+g][j]
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) t[s] = mfma16(-pa[q], pb[q], t[s]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __syncthreads();
+        }
+        // a failed pivot is reported after all steps: the steps only ever
+        // address tiles by slot, so values gone bad are harmless, and a second
+        // exit from the loop would split the tiles' live ranges
+        if (!sh_flag) {
+            if (tid == 0) atomicMin(bad_row, (int)k);
+            for (int64_t e = tid; e < (int64_t)m * b * b; e += RR_NT) g_vals[p0 * b * b + e] = 0.0;
+            __syncthreads();
+            continue;
+        }
+        // V by tile columns j descending; S_a = sum_{b > a} V_b W_ab^T gathers
+        // in pu, one term per step in a fixed order, and V_{jt-1} = -S_{jt-1}
+        // is finished by the wavefront adding the last term
+        for (int jt = T - 1; jt >= 1; --jt) {
+#pragma unroll
+            for (int s = 0; s < RR_SLOTS; ++s) {
+                const int v = slot_word(ab[s]);
+                const int a = v >> 8, bt = v & 255;
+                if (v >= 0 && bt == jt && a < jt) {
+                    v4d acc;
+                    if (jt == T - 1) {
+                        acc = t[s];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) acc[q] = pu[a * 256 + 64 * q + lane];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            acc = mfma16(vv[jt * 256 + j * 16 + 4 * q + g], t[s][q], acc);   // V_jt[j][4q+g]
+                    }
+                    if (a == jt - 1) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) vv[a * 256 + 64 * q + lane] = -acc[q];
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) pu[a * 256 + 64 * q + lane] = acc[q];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            __syncthreads();
+        }
+        // X V by tile columns (V_{T-1} = I)
+        for (int a = w; a < T; a += RR_WAVES) {
+            v4d y = {0.0, 0.0, 0.0, 0.0};
+            if (a == T - 1) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y[q] = dinv[64 * q + lane];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) y = mfma16(dinv[j * 16 + 4 * q + g], vv[a * 256 + 64 * q + lane], y);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) vv[a * 256 + 64 * q + lane] = y[q];
+        }
+        __syncthreads();
+        // G_k[t][x b + cc] = row 16 - b + t of the last tile row, column pad + x b + cc
+        const int bb = b * b;
+        for (int e = tid; e < m * bb; e += RR_NT) {
+            const int x = e / bb, rem = e - x * bb;
+            const int tr = rem / b, cc = rem - tr * b;
+            const int p = pad + x * b + cc;
+            g_vals[(p0 + x) * bb + rem] = vv[(p >> 4) * 256 + (16 - b + tr) * 16 + (p & 15)];
+        }
+        __syncthreads();
+    }
+}
+
 // Persistent kernel: each workgroup pops rows (ordered by decreasing local
-// size) from a global counter until the queue is empty. Per row, by size:
+// size, less the range [skip_lo, skip_lo + skip_len) of the order) from a
+// global counter until the queue is empty. Per row, by size:
 // the tiled MFMA solver (n > ntile, 256-wide workgroups, b <= 16), the
 // scalar solver in LDS (n <= nlds), or the scalar solver in the workgroup's
 // global scratch slot.
@@ -472,7 +946,7 @@ __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t*
                                                    const int64_t* __restrict__ p_rowptr, const int* __restrict__ p_col,
                                                    double* __restrict__ g_vals, int nlds, int ntile, int tmaxtiles,
                                                    double* scratch, int64_t scratch_stride, int* counter,
-                                                   int* bad_row) {
+                                                   int* bad_row, int64_t skip_lo, int64_t skip_len) {
     extern __shared__ double lds[];
     __shared__ int idx[FSAI_MAXM * FSAI_MAXM];
     __shared__ double sh_scal[1];
@@ -485,9 +959,10 @@ __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t*
     for (;;) {
         if (threadIdx.x == 0) sh_next = atomicAdd(counter, 1);
         __syncthreads();
-        const int64_t it = sh_next;
+        int64_t it = sh_next;
         __syncthreads();
         if (it >= nrows) break;
+        if (it >= skip_lo) it += skip_len;   // order[skip_lo .. skip_lo + skip_len) went to another kernel
         const int64_t k = order[it];
         const int n = (int)(p_rowptr[k + 1] - p_rowptr[k]) * b;
         if constexpr (NT == 256) {
@@ -511,16 +986,17 @@ __global__ __launch_bounds__(NT) void k_fsai_setup(int64_t nrows, const int64_t*
 }
 
 // ------------------------------------------------------------ autotuning --
-// A configuration is a workgroup width (64, 128, 256) and a size threshold
-// above which rows take the tiled MFMA path (256-wide only). The best one for
-// (b, largest local size) is picked by timing the persistent kernel on an
+// A configuration is a workgroup width (64, 128, 256), a size threshold
+// above which rows take the tiled MFMA path (256-wide only), and a threshold
+// above which rows of at most RR_MAXN take the register-resident kernel. The
+// best one for (b, largest local size) is picked by timing the set-up on an
 // evenly strided sample of the rows, and cached for the process.
 struct TuneKey {
     int b, nmax;
     bool operator<(const TuneKey& o) const { return b != o.b ? b < o.b : nmax < o.nmax; }
 };
 struct TuneVal {
-    int nt, ntile;
+    int nt, ntile, rr_lo;
 };
 static std::map<TuneKey, TuneVal> g_tuned;
 static std::mutex g_tune_mu;
@@ -540,6 +1016,8 @@ struct SetupArgs {
     int* counter;
     int* bad_row;
     int nmax;
+    const int* nsz;      // host: local size of order[i], non-increasing
+    int* xcd_counters;   // 8 counters of the register-resident kernel
 };
 
 static size_t lds_bytes(int nlds, int b) {
@@ -570,6 +1048,24 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s, DevBuf<
     const size_t need = (a.nmax > nlds || tiled) ? (size_t)grid * stride : 1;
     if (scratch.n < need) scratch.alloc(need);
     double* scr = scratch.p;
+    // rows with rr_lo < n <= RR_MAXN: one contiguous range of the size-sorted order
+    int64_t rr0 = 0, rr1 = 0;
+    if (cfg.rr_lo < NO_TILES && a.b <= 16) {
+        rr0 = std::partition_point(a.nsz, a.nsz + a.nrows, [](int v) { return v > RR_MAXN; }) - a.nsz;
+        rr1 = std::partition_point(a.nsz, a.nsz + a.nrows, [&](int v) { return v > cfg.rr_lo; }) - a.nsz;
+        rr1 = std::max(rr1, rr0);
+    }
+    if (rr1 > rr0) {
+        fill_zero(a.xcd_counters, 8 * sizeof(int), s);
+        const int bmul = (65536 + a.b - 1) / a.b;
+        hipLaunchKernelGGL(k_fsai_setup_rr, dim3((unsigned)std::min<int64_t>(cus, rr1 - rr0)), dim3(RR_NT), 0, s,
+                           rr1 - rr0, a.order + rr0, a.b, bmul, a.a_rowptr, a.a_col, a.a_vals, a.p_rowptr, a.p_col,
+                           a.g_vals, a.xcd_counters, a.bad_row);
+        CHF_LAUNCH_CHECK();
+    }
+    const int64_t rest = a.nrows - (rr1 - rr0);
+    if (rest == 0) return;
+    grid = std::min<int64_t>(grid, rest);
     fill_zero(a.counter, sizeof(int), s);
     if (shm > 64 * 1024) {
         CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
@@ -577,9 +1073,11 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s, DevBuf<
         CHF_HIP(hipFuncSetAttribute((const void*)k_fsai_setup<256>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     }
     auto go = [&](auto kern, int nt) {
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), shm, s, a.nrows, a.order, a.b, a.a_rowptr, a.a_col, a.a_vals,
+        // the queue holds the `rest` rows outside [rr0, rr1): popped indices
+        // at or above rr0 are shifted past that range, so stay below nrows
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), shm, s, rest, a.order, a.b, a.a_rowptr, a.a_col, a.a_vals,
                            a.p_rowptr, a.p_col, a.g_vals, nlds, cfg.ntile, tmaxtiles, scr, stride, a.counter,
-                           a.bad_row);
+                           a.bad_row, rr0, rr1 - rr0);
     };
     switch (cfg.nt) {
         case 64: go(k_fsai_setup<64>, 64); break;
@@ -591,10 +1089,11 @@ static void launch_setup(TuneVal cfg, const SetupArgs& a, hipStream_t s, DevBuf<
 
 static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order_host, hipStream_t s) {
     const int nmax = a.nmax;
-    if (const char* env = std::getenv("CHF_FSAI_CONFIG")) {   // "<width>,<tile threshold>"
-        int w = 0, t = 0;
-        if (std::sscanf(env, "%d,%d", &w, &t) == 2 && (w == 64 || w == 128 || w == 256))
-            return TuneVal{w, t > 0 ? t : NO_TILES};
+    if (const char* env = std::getenv("CHF_FSAI_CONFIG")) {   // "<width>,<tile threshold>[,<rr threshold>]"
+        int w = 0, t = 0, r = -1;
+        const int got = std::sscanf(env, "%d,%d,%d", &w, &t, &r);
+        if (got >= 2 && (w == 64 || w == 128 || w == 256))
+            return TuneVal{w, t > 0 ? t : NO_TILES, got == 3 && r >= 0 ? r : NO_TILES};
     }
     TuneKey key{a.b, nmax};
     {
@@ -602,27 +1101,39 @@ static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) return it->second;
     }
-    std::vector<TuneVal> cands = {{64, NO_TILES}, {128, NO_TILES}, {256, NO_TILES}};
+    std::vector<TuneVal> cands = {{64, NO_TILES, NO_TILES}, {128, NO_TILES, NO_TILES}, {256, NO_TILES, NO_TILES}};
     if (a.b <= 16 && nmax > 32) {
-        cands.push_back({256, 32});
-        if (nmax > 48) cands.push_back({256, 48});
-        if (nmax > 96) cands.push_back({256, 96});
-        if (nmax > 160) cands.push_back({256, 160});
+        cands.push_back({256, 32, NO_TILES});
+        if (nmax > 48) cands.push_back({256, 48, NO_TILES});
+        if (nmax > 96) cands.push_back({256, 96, NO_TILES});
+        if (nmax > 160) cands.push_back({256, 160, NO_TILES});
+        // the register-resident kernel for the rows above 96 or 160, the rest as tuned above
+        const size_t nbase = cands.size();
+        for (int lo : {96, 160}) {
+            if (nmax <= lo) continue;
+            for (size_t i = 0; i < nbase; ++i) cands.push_back({cands[i].nt, cands[i].ntile, lo});
+        }
     }
-    TuneVal best = nmax > 64 ? TuneVal{128, NO_TILES} : TuneVal{64, NO_TILES};
+    TuneVal best = nmax > 64 ? TuneVal{128, NO_TILES, NO_TILES} : TuneVal{64, NO_TILES, NO_TILES};
     if (a.nrows >= 4096) {
         // evenly strided samples of the size-sorted order keep the size mix
-        auto sample = [&](int64_t ns) {
+        auto sample = [&](int64_t ns, std::vector<int>& sz) {
             std::vector<int64_t> o(std::min<int64_t>(ns, a.nrows));
-            for (size_t i = 0; i < o.size(); ++i) o[i] = order_host[(int64_t)i * a.nrows / (int64_t)o.size()];
+            sz.resize(o.size());
+            for (size_t i = 0; i < o.size(); ++i) {
+                const int64_t pos = (int64_t)i * a.nrows / (int64_t)o.size();
+                o[i] = order_host[pos];
+                sz[i] = a.nsz[pos];
+            }
             return o;
         };
         DevBuf<double> scratch;
         // seconds of one launch on `rows` (device order), after a warm-up launch
-        auto time_on = [&](const TuneVal& c, const DevBuf<int64_t>& rows, int64_t n) {
+        auto time_on = [&](const TuneVal& c, const DevBuf<int64_t>& rows, int64_t n, const std::vector<int>& sz) {
             SetupArgs smp = a;
             smp.nrows = n;
             smp.order = rows.p;
+            smp.nsz = sz.data();
             launch_setup(c, smp, s, scratch);
             CHF_HIP(hipStreamSynchronize(s));
             auto t0 = std::chrono::steady_clock::now();
@@ -632,20 +1143,21 @@ static TuneVal pick_config(const SetupArgs& a, const std::vector<int64_t>& order
         };
         // screening on 1,024 rows drops candidates more than twice as slow as
         // the best one (the scalar solvers on wide rows are tens of times slower)
-        const std::vector<int64_t> small = sample(1024), full = sample(8192);
+        std::vector<int> sz_small, sz_full;
+        const std::vector<int64_t> small = sample(1024, sz_small), full = sample(8192, sz_full);
         DevBuf<int64_t> d_small(small.size()), d_full(full.size());
         d_small.upload(small.data(), small.size(), s);
         d_full.upload(full.data(), full.size(), s);
         std::vector<double> ts(cands.size());
         double ts_best = 1e30;
         for (size_t i = 0; i < cands.size(); ++i) {
-            ts[i] = time_on(cands[i], d_small, (int64_t)small.size());
+            ts[i] = time_on(cands[i], d_small, (int64_t)small.size(), sz_small);
             ts_best = std::min(ts_best, ts[i]);
         }
         double best_t = 1e30;
         for (size_t i = 0; i < cands.size(); ++i) {
             if (ts[i] > 2.0 * ts_best) continue;
-            const double dt = time_on(cands[i], d_full, (int64_t)full.size());
+            const double dt = time_on(cands[i], d_full, (int64_t)full.size(), sz_full);
             if (dt < best_t) { best_t = dt; best = cands[i]; }
         }
     }
@@ -744,9 +1256,11 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
     std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
         return P.rowptr[x + 1] - P.rowptr[x] > P.rowptr[y + 1] - P.rowptr[y];
     });
+    std::vector<int> nsz(nb);
+    for (int64_t i = 0; i < nb; ++i) nsz[i] = (int)(P.rowptr[order[i] + 1] - P.rowptr[order[i]]) * b;
     std::vector<int> pcol32(P.colidx.begin(), P.colidx.end());
     DevBuf<int64_t> d_order(std::max<int64_t>(1, nb)), d_prow(nb + 1);
-    DevBuf<int> d_pcol(std::max<int64_t>(1, G->nnz)), d_flags(2);
+    DevBuf<int> d_pcol(std::max<int64_t>(1, G->nnz)), d_flags(10);   // counter, bad row, 8 XCD counters
     d_order.upload(order.data(), nb, s);
     d_prow.upload(P.rowptr.data(), nb + 1, s);
     d_pcol.upload(pcol32.data(), G->nnz, s);
@@ -755,7 +1269,8 @@ chf_fsai_s* fsai_setup_impl(chf_bsr A, const chf_pattern_s& P, chf_dtype g_store
     G->d_vals.alloc(std::max<int64_t>(1, G->nnz * b * b));
     if (nb > 0) {
         SetupArgs args{nb, d_order.p, b, A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, d_prow.p, d_pcol.p,
-                       G->d_vals.p, std::min(max_lds_n(b), nmax), d_flags.p, d_flags.p + 1, nmax};
+                       G->d_vals.p, std::min(max_lds_n(b), nmax), d_flags.p, d_flags.p + 1, nmax, nsz.data(),
+                       d_flags.p + 2};
         TuneVal cfg = pick_config(args, order, s);
         DevBuf<double> scratch;
         launch_setup(cfg, args, s, scratch);

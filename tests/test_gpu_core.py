@@ -136,9 +136,11 @@ def test_lanczos_bound(chf):
 # With '256,1' every row goes through the tiled solver, which factors pairs of
 # tile columns: at b = 10 the failing pivot of row 1 (row 10 of a 20-wide
 # system) lies in tile column 0, the first of a pair, and that of row 17 (row
-# 50 of a 60-wide system) in tile column 3, the second of a pair.
+# 50 of a 60-wide system) in tile column 3, the second of a pair. With
+# '256,1,0' every row goes through the register-resident kernel, which meets
+# the failing pivot in the inverse of its last diagonal tile.
 @pytest.mark.parametrize("b,k", [(3, 17), (10, 1), (10, 17)])
-@pytest.mark.parametrize("config", [None, "256,1"])
+@pytest.mark.parametrize("config", [None, "256,1", "256,1,0"])
 def test_error_not_spd_reports_row(chf, b, k, config, monkeypatch):
     if config:
         monkeypatch.setenv("CHF_FSAI_CONFIG", config)
@@ -200,11 +202,13 @@ def test_run_twice_bit_identical(chf):
 
 
 @pytest.mark.parametrize("n,dim,b,pw,tmax", [(9, 2, 10, 2, 8), (4, 3, 10, 2, 23), (8, 2, 3, 2, 12), (7, 2, 1, 2, 20)])
-@pytest.mark.parametrize("config", ["256,1", "256,48", "64,0", "128,0"])
+@pytest.mark.parametrize("config", ["256,1", "256,48", "64,0", "128,0", "256,1,0", "256,48,96"])
 def test_fsai_configs_match_oracle(chf, n, dim, b, pw, tmax, config, monkeypatch):
-    """Every solver configuration (width, tiled-MFMA threshold) gives the
-    oracle's G; '256,1' sends every row through the tiled MFMA path, and the
-    3D t_max = 23 case has local systems up to 240 wide."""
+    """Every solver configuration (width, tiled-MFMA threshold, register-
+    resident threshold) gives the oracle's G; '256,1' sends every row through
+    the tiled MFMA path, '256,1,0' every row of at most 240 through the
+    register-resident kernel (from 1 to 15 tiles), and the 3D t_max = 23 case
+    has local systems up to 240 wide."""
     from oracle import adaptive
     p = make_problem(n, dim, b, pw, seed=0)
     a = from_problem(p)
