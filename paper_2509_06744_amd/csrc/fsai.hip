@@ -576,6 +576,55 @@ __device__ __forceinline__ bool chol_inv4(const double (&P)[4][4], int g, int j,
     return ok;
 }
 
+// P^{-1}[j][g] of a 4 x 4 SPD pivot P (the same on every lane; lower triangle
+// used) for the padded operand (zero for j >= 4), by P = L D L^T with L unit
+// lower: P^{-1} = Y^T D^{-1} Y with Y = L^{-1}; reciprocals only, no square
+// roots. (Closed-form 2 x 2 block inverses are shorter but lose up to three
+// more digits on ill-conditioned pivots.) False if a pivot is not positive
+// and finite.
+__device__ __forceinline__ bool spd_inv4(const double (&P)[4][4], int g, int j, double& pin) {
+    double L[4][4], e[4][4], r[4];
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        double d = P[c][c];
+#pragma unroll
+        for (int t = 0; t < c; ++t) d -= L[c][t] * e[c][t];
+        ok = ok && (d > 0.0) && isfinite(d);
+        r[c] = rcp_nr(fmax(d, 1e-300));
+#pragma unroll
+        for (int i = c + 1; i < 4; ++i) {
+            double v = P[i][c];
+#pragma unroll
+            for (int t = 0; t < c; ++t) v -= L[i][t] * e[c][t];
+            e[i][c] = v;
+            L[i][c] = v * r[c];
+        }
+    }
+    double Y[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) Y[i][c] = c == i ? 1.0 : 0.0;
+#pragma unroll
+        for (int c = 0; c < i; ++c) {
+            double v = L[i][c];
+#pragma unroll
+            for (int t = c + 1; t < i; ++t) v += L[i][t] * Y[t][c];
+            Y[i][c] = -v;
+        }
+    }
+    double pi = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const double yj = sel4(j, Y[t][0], Y[t][1], Y[t][2], Y[t][3]);
+        const double yg = sel4(g, Y[t][0], Y[t][1], Y[t][2], Y[t][3]);
+        pi = fma(yj * r[t], yg, pi);
+    }
+    pin = j < 4 ? pi : 0.0;
+    return ok;
+}
+
 // In place on an SPD tile M in accumulator layout (one wavefront), by 4 x 4
 // blocks p with pivot P (entry (i, c) of P sits in element p of lane
 // 16 i + 4 p + c):
@@ -610,8 +659,11 @@ __device__ inline bool tile_inverse(v4d& m, int lane) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int c = 0; c <= i; ++c) P[i][c] = lane_bcast(m[blk], 16 * i + 4 * blk + c);
-        double pin, xin;
-        ok = chol_inv4(P, g, j, pin, xin) && ok;
+        double pin, xin = 0.0;
+        if constexpr (chol)
+            ok = chol_inv4(P, g, j, pin, xin) && ok;
+        else
+            ok = spd_inv4(P, g, j, pin) && ok;
         const bool dg = j == 4 * blk + g;
         const double lam = 0.25 * (P[0][0] + P[1][1] + P[2][2] + P[3][3]);
         const double sw = m[blk] - (dg ? lam : 0.0);
@@ -652,6 +704,10 @@ __device__ __forceinline__ int slot_word(int v) {
     return v;
 }
 
+// The constants a tile element takes where it has no entry of A: 0, or 1 on
+// the diagonal of the padding.
+__device__ double rr_zero_one[2] = {0.0, 1.0};   // global, like A, so the loads stay global loads
+
 // Persistent: one workgroup per CU pops rows of order[0 .. nrows). The order
 // is cut into chunks of RR_CHUNK consecutive rows (neighbours in space, which
 // share most blocks of A), and chunk c goes to XCD c % nx (workgroups are
@@ -666,13 +722,19 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
                                                          const int64_t* __restrict__ p_rowptr,
                                                          const int* __restrict__ p_col, double* __restrict__ g_vals,
                                                          int* xcd_counters, int* bad_row) {
-    __shared__ int idx[FSAI_MAXM * FSAI_MAXM];
-    __shared__ double pu[RR_TMAX * 256];   // U_c. of the panel row; S in the back-substitution
-    __shared__ double pw[RR_TMAX * 256];   // W_c. of the panel row
-    __shared__ double vv[RR_TMAX * 256];   // V, then X V
-    __shared__ double dinv[256];           // D_c^{-1}; X = R_{T-1}^{-1} at the end
-    __shared__ int sh_flag;
+    constexpr int PANEL = RR_TMAX * 256;
+    // panel row c in buffer c & 1 (-U_c. and W_c.); the block map lives in pw's
+    // buffer 1 during the fill, V in pw's buffer 0 and S in pu's buffer 0
+    // during the back-substitution
+    __shared__ double pu[2 * PANEL];
+    __shared__ double pw[2 * PANEL];
+    __shared__ double dg[PANEL];        // the diagonal tiles U_aa
+    __shared__ double dinv[2 * 256];    // D_a^{-1} in buffer a & 1; X = R_{T-1}^{-1} for a = T - 1
+    __shared__ int sh_flag, f_dinv, f_wcrit, f_diag;
     __shared__ int64_t sh_next;
+    int* idx = reinterpret_cast<int*>(pw + PANEL);
+    double* vv = pw;
+    static_assert(FSAI_MAXM * FSAI_MAXM * sizeof(int) <= PANEL * sizeof(double), "block map must fit");
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, j = lane & 15;
@@ -729,193 +791,290 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
                 if (t < m * m) idx[t] = (want[s] >= 0 && lo[s] < end[s] && a_col[lo[s]] == want[s]) ? lo[s] : -1;
             }
         }
-        if (tid == 0) sh_flag = 1;
+        if (tid == 0) {
+            sh_flag = 1;
+            f_dinv = f_wcrit = f_diag = -1;
+        }
         __syncthreads();
-        // Tiles of this wavefront. Diagonal tiles (a, a): wavefront a % 8,
-        // slot a / 8. The off-diagonal tiles, listed by tile row descending and
-        // column ascending, are dealt in turn starting at wavefront T % 8 (the
-        // first with one diagonal tile fewer), after the diagonal slots. Slot s
-        // holds tile (ab[s] >> 8, ab[s] & 255); ab[s] < 0 if unused.
-        int ab[RR_SLOTS];
-        {
-            const int ndiag = w < T ? (T - 1 - w) / 8 + 1 : 0;
-            const int rot = (w - (T & 7) + 8) & 7;
-            const int noff = T * (T - 1) / 2;
+        // Element (4q + g, j) of tile U_ab is Kpad[16 a + 4q + g][16 b + j].
+        // Each element is one load straight into its register, from A or, for
+        // a missing block, a padding entry or an unused slot, from the
+        // constants {0, 1}: no branches and nothing to do after the loads,
+        // so all of them are in flight together.
+        auto tile_load = [&](int a, int bt, bool use, v4d& t) {
+            const int pc = 16 * bt + j - pad;
+            const int pcc = max(pc, 0);
+            const int y = (pcc * bmul) >> 16, ry = pcc - y * b;
 #pragma unroll
-            for (int s = 0; s < RR_SLOTS; ++s) {
-                int v = -1;
-                if (s < ndiag) {
-                    v = (w + 8 * s) * 257;
-                } else {
-                    const int i = 8 * (s - ndiag) + rot;
+            for (int q = 0; q < 4; ++q) {
+                const int pr = 16 * a + 4 * q + g - pad;
+                const int prc = max(pr, 0);
+                const int x = (prc * bmul) >> 16, rx = prc - x * b;
+                const int e = idx[x * m + y];   // clamped positions are in range
+                const bool real = pr >= 0 && pc >= 0;
+                const double* src = use && real && e >= 0
+                                        ? a_vals + ((int64_t)e * b * b + rx * b + ry)
+                                        : rr_zero_one + ((use && !real && pr == pc) ? 1 : 0);
+                t[q] = *src;
+            }
+        };
+        // Roles. Wavefront 0 runs the chain of diagonal inverses and holds no
+        // tile. The diagonal tiles sit in LDS, tile a updated by wavefront
+        // 1 + a % 7. The off-diagonal tiles, listed by tile row descending and
+        // column ascending, are dealt in turn to wavefronts 1..7: slot s of
+        // wavefront w holds list entry 7 s + w - 1. The two roles run separate
+        // loops that cross the same barriers in the same order (every count
+        // below depends on T only), so that the tiles' registers are not live
+        // in the chain's code and the inverse's temporaries not in the tiles'.
+        //
+        // Steps c = -1 .. T - 2 (block LDL^T with a look-ahead of one step),
+        // one barrier each; n1 = c + 1, n2 = c + 2. At the start of step c,
+        // panel row c is in buffer c & 1 and D_{n1}^{-1} is ready (step -1
+        // makes D_0^{-1} itself). In step c:
+        //  - the owner of U_{n1,n2} updates it with panel row c, forms
+        //    W_{n1,n2} = D_{n1}^{-1} U_{n1,n2} at once and publishes it
+        //    (f_wcrit); the updater of U_{n2,n2} updates it with panel row c
+        //    and publishes that (f_diag);
+        //  - the chain takes D_{n2} = U_{n2,n2} - U_{n1,n2}^T W_{n1,n2} (its
+        //    last update) and inverts it, the last one (T - 1) by its Cholesky
+        //    factor, while
+        //  - the others update their tiles with panel row c and then write
+        //    panel row n1 to buffer n1 & 1, their tiles becoming W^T.
+        // D^{-1} is stored symmetrised: its rounding asymmetry would otherwise
+        // grow step by step through the Schur updates.
+        auto wait_eq = [&](int* f, int v) {   // bounded; a wait that runs out fails the row
+            for (int spin = 0; __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != v; ++spin) {
+                if (spin > (1 << 14)) {
+                    if (lane == 0) sh_flag = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        };
+        auto publish = [&](int* f, int v) { __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); };
+        for (int a = w; a < T; a += RR_WAVES) {
+            v4d d;
+            tile_load(a, a, true, d);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dg[a * 256 + 64 * q + lane] = d[q];
+        }
+        bool ok_row;
+        if (w == 0) {
+            // ----------------------------------------------------- the chain
+            __syncthreads();
+            for (int c = -1; c + 1 < T; ++c) {
+                const int n2 = c + 2;
+                // step -1 inverts D_0 (and publishes it), then D_1; later steps D_{n2}
+#pragma unroll 1
+                for (int a = c < 0 ? 0 : n2; a <= n2 && a < T; ++a) {
+                    const double* pua = pu + ((a - 1) & 1) * PANEL;   // panel row a - 1
+                    const double* pwa = pw + ((a - 1) & 1) * PANEL;
+                    if (a > 0) {
+                        wait_eq(&f_wcrit, a - 1);
+                        wait_eq(&f_diag, a);
+                    }
+                    v4d d;   // read only once its updater has published it
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) d[q] = dg[a * 256 + 64 * q + lane];
+                    if (a > 0) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)   // the panel holds -U
+                            d = mfma16(pua[a * 256 + 64 * q + lane], pwa[a * 256 + 64 * q + lane], d);
+                    }
+                    double* di = dinv + (a & 1) * 256;   // D_a^{-1}, or X for a = T - 1
+                    bool ok;
+                    if (a + 1 < T) {
+                        ok = tile_inverse<false>(d, lane);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) di[64 * q + lane] = d[q];
+                        double dt[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dt[q] = di[j * 16 + 4 * q + g];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) di[64 * q + lane] = 0.5 * (d[q] + dt[q]);
+                    } else {
+                        ok = tile_inverse<true>(d, lane);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) di[64 * q + lane] = d[q];
+                    }
+                    if (!ok && lane == 0) sh_flag = 0;
+                    if (a == 0) publish(&f_dinv, 0);
+                }
+                __syncthreads();
+            }
+            ok_row = sh_flag != 0;
+            if (ok_row) {
+                for (int jt = T - 1; jt >= 1; --jt) __syncthreads();   // the back-substitution's barriers
+            }
+        } else {
+            // ------------------------------------------------------ the tiles
+            int ab[RR_SLOTS];   // slot s: tile (ab[s] >> 8, ab[s] & 255); < 0 if unused
+            {
+                const int noff = T * (T - 1) / 2;
+#pragma unroll
+                for (int s = 0; s < RR_SLOTS; ++s) {
+                    int v = -1;
+                    const int i = 7 * s + w - 1;
                     if (i < noff) {
                         int r, o;
                         tri_decode(i, r, o);
                         v = (T - 2 - r) * 256 + (T - 1 - r + o);
                     }
-                }
-                ab[s] = __builtin_amdgcn_readfirstlane(v);
-            }
-        }
-        // fill: element (4q + g, j) of U_ab is Kpad[16 a + 4q + g][16 b + j]
-        v4d t[RR_SLOTS];
-#pragma unroll
-        for (int s = 0; s < RR_SLOTS; ++s) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) t[s][q] = 0.0;
-            if (ab[s] >= 0) {
-                // every lane loads (padding lanes entry 0 of A), then selects
-                const int a = ab[s] >> 8, bt = ab[s] & 255;
-                const int pc = 16 * bt + j - pad;
-                const int pcc = max(pc, 0);
-                const int y = (pcc * bmul) >> 16, ry = pcc - y * b;
-                int e[4];
-                int64_t off[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int pr = 16 * a + 4 * q + g - pad;
-                    const int prc = max(pr, 0);
-                    const int x = (prc * bmul) >> 16, rx = prc - x * b;
-                    e[q] = (pr >= 0 && pc >= 0) ? idx[x * m + y] : -1;
-                    off[q] = e[q] >= 0 ? (int64_t)e[q] * b * b + rx * b + ry : 0;
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double v = a_vals[off[q]];
-                    const int pr = 16 * a + 4 * q + g - pad;
-                    t[s][q] = e[q] >= 0 ? v : ((pr == pc) ? 1.0 : 0.0);
+                    ab[s] = __builtin_amdgcn_readfirstlane(v);
                 }
             }
-        }
-        // Steps c = -1 .. T - 2. Step c >= 0: panel row c (W_cb = Dinv U_cb to
-        // LDS with U_cb; the tile becomes W_cb^T for the back-substitution), then
-        // the trailing update. In every step the owner of the next diagonal
-        // tile dn = c + 1 updates it first and inverts it (the last one by its
-        // Cholesky factor) while the others update their tiles.
-        for (int c = -1; c + 1 < T; ++c) {
-            if (c >= 0) {
-                double xa[4];
+            v4d t[RR_SLOTS];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) xa[q] = dinv[64 * q + lane];   // Dinv[j][4q+g] (symmetric)
+            for (int s = 0; s < RR_SLOTS; ++s) {
+                const bool use = ab[s] >= 0;   // unused slots read zeros through tile (0, 0)
+                tile_load(use ? ab[s] >> 8 : 0, use ? ab[s] & 255 : 0, use, t[s]);
+            }
+            __syncthreads();
+            for (int c = -1; c + 1 < T; ++c) {
+                const int n1 = c + 1, n2 = c + 2;
+                const double* puc = pu + (c & 1) * PANEL;
+                const double* pwc = pw + (c & 1) * PANEL;
+                double* pun = pu + (n1 & 1) * PANEL;
+                double* pwn = pw + (n1 & 1) * PANEL;
+                const double* din1 = dinv + (n1 & 1) * 256;
+                if (c < 0) wait_eq(&f_dinv, 0);
+                // panel tile of row n1: W = Dinv U and W^T = U^T Dinv
+                auto panel = [&](v4d& tt, int bt) {
+                    double xa[4];   // D_{n1}^{-1}[j][4q+g] (symmetric)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) xa[q] = din1[64 * q + lane];
+                    v4d wv = {0.0, 0.0, 0.0, 0.0}, wt = wv;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        wv = mfma16(xa[q], tt[q], wv);
+                        wt = mfma16(tt[q], xa[q], wt);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        pun[bt * 256 + 64 * q + lane] = -tt[q];   // -U: the updates then accumulate
+                        pwn[bt * 256 + 64 * q + lane] = wv[q];
+                    }
+                    tt = wt;
+                };
+                // U_ab -= U_ca^T W_cb with panel row c (its U held negated)
+                auto update = [&](v4d& tt, int a, int bt) {
+                    double pa[4], pb[4];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        pa[q] = puc[a * 256 + 64 * q + lane];    // -U_ca^T[j][4q+g]
+                        pb[q] = pwc[bt * 256 + 64 * q + lane];   // W_cb[4q+g][j]
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tt = mfma16(pa[q], pb[q], tt);
+                };
+                if (n2 < T) {
+                    // the critical tile (n1, n2) first
+#pragma unroll
+                    for (int s = 0; s < RR_SLOTS; ++s) {
+                        if (slot_word(ab[s]) == n1 * 256 + n2) {
+                            if (c >= 0) update(t[s], n1, n2);
+                            panel(t[s], n2);
+                            publish(&f_wcrit, n1);
+                        }
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                    // then the diagonal tile n2
+                    if (w == 1 + n2 % 7) {
+                        if (c >= 0) {
+                            v4d d;
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) d[q] = dg[n2 * 256 + 64 * q + lane];
+                            update(d, n2, n2);
+#pragma unroll
+                            for (int q = 0; q < 4; ++q) dg[n2 * 256 + 64 * q + lane] = d[q];
+                        }
+                        publish(&f_diag, n2);
+                    }
+                }
+                if (c >= 0) {
+                    // the other diagonal tiles still to come (a > n2)
+                    for (int a = n2 + 1; a < T; ++a) {
+                        if (w != 1 + a % 7) continue;
+                        v4d d;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) d[q] = dg[a * 256 + 64 * q + lane];
+                        update(d, a, a);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dg[a * 256 + 64 * q + lane] = d[q];
+                    }
+                    // the off-diagonal tiles
+#pragma unroll
+                    for (int s = 0; s < RR_SLOTS; ++s) {
+                        const int v = slot_word(ab[s]);
+                        const int a = v >> 8, bt = v & 255;
+                        if (v >= 0 && a > c && v != n1 * 256 + n2) update(t[s], a, bt);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+                // panel row n1 (but the critical tile)
 #pragma unroll
                 for (int s = 0; s < RR_SLOTS; ++s) {
                     const int v = slot_word(ab[s]);
                     const int a = v >> 8, bt = v & 255;
-                    if (v >= 0 && a == c && bt > c) {
-                        // W = Dinv U and W^T = U^T Dinv: the same operands swapped
-                        v4d wv = {0.0, 0.0, 0.0, 0.0}, wt = wv;
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            wv = mfma16(xa[q], t[s][q], wv);
-                            wt = mfma16(t[s][q], xa[q], wt);
-                        }
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            pu[bt * 256 + 64 * q + lane] = t[s][q];
-                            pw[bt * 256 + 64 * q + lane] = wv[q];
-                        }
-                        t[s] = wt;
-                    }
+                    if (v >= 0 && a == n1 && bt > n2) panel(t[s], bt);
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 __syncthreads();
             }
-            const int dn = c + 1;
-            if (w == (dn & 7)) {
-                v4d d = dn < 8 ? t[0] : t[1];
-                if (c >= 0) {
+            // a failed pivot is reported after all steps: the steps only ever
+            // address tiles by slot, so values gone bad are harmless
+            ok_row = sh_flag != 0;
+            if (ok_row) {
+                // V by tile columns jt descending; S_a = sum_{b > a} V_b W_ab^T
+                // gathers in pu, one term per step in a fixed order, and
+                // V_{jt-1} = -S_{jt-1} is finished by the wavefront adding the
+                // last term
+                for (int jt = T - 1; jt >= 1; --jt) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        d = mfma16(-pu[dn * 256 + 64 * q + lane], pw[dn * 256 + 64 * q + lane], d);
-                }
-                bool ok;
-                if (dn + 1 < T) {
-                    // D^{-1}, stored symmetrised: its rounding asymmetry would
-                    // otherwise grow step by step through the Schur updates
-                    ok = tile_inverse<false>(d, lane);
+                    for (int s = 0; s < RR_SLOTS; ++s) {
+                        const int v = slot_word(ab[s]);
+                        const int a = v >> 8, bt = v & 255;
+                        if (v >= 0 && bt == jt && a < jt) {
+                            v4d acc;
+                            if (jt == T - 1) {
+                                acc = t[s];
+                            } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) dinv[64 * q + lane] = d[q];
-                    double dt[4];
+                                for (int q = 0; q < 4; ++q) acc[q] = pu[a * 256 + 64 * q + lane];
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) dt[q] = dinv[j * 16 + 4 * q + g];
+                                for (int q = 0; q < 4; ++q)
+                                    acc = mfma16(vv[jt * 256 + j * 16 + 4 * q + g], t[s][q], acc);   // V_jt[j][4q+g]
+                            }
+                            if (a == jt - 1) {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) dinv[64 * q + lane] = 0.5 * (d[q] + dt[q]);
-                } else {
-                    ok = tile_inverse<true>(d, lane);
+                                for (int q = 0; q < 4; ++q) vv[a * 256 + 64 * q + lane] = -acc[q];
+                            } else {
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) dinv[64 * q + lane] = d[q];
-                }
-                if (!ok && lane == 0) sh_flag = 0;
-            }
-            if (c >= 0) {
-#pragma unroll
-                for (int s = 0; s < RR_SLOTS; ++s) {
-                    const int v = slot_word(ab[s]);
-                    const int a = v >> 8, bt = v & 255;
-                    if (v >= 0 && a > c && !(a == dn && bt == dn)) {
-                        double pa[4], pb[4];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            pa[q] = pu[a * 256 + 64 * q + lane];    // U_ca^T[j][4q+g]
-                            pb[q] = pw[bt * 256 + 64 * q + lane];   // W_cb[4q+g][j]
+                                for (int q = 0; q < 4; ++q) pu[a * 256 + 64 * q + lane] = acc[q];
+                            }
                         }
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) t[s] = mfma16(-pa[q], pb[q], t[s]);
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    __builtin_amdgcn_sched_barrier(0);
+                    __syncthreads();
                 }
             }
-            __syncthreads();
         }
-        // a failed pivot is reported after all steps: the steps only ever
-        // address tiles by slot, so values gone bad are harmless, and a second
-        // exit from the loop would split the tiles' live ranges
-        if (!sh_flag) {
+        if (!ok_row) {
             if (tid == 0) atomicMin(bad_row, (int)k);
             for (int64_t e = tid; e < (int64_t)m * b * b; e += RR_NT) g_vals[p0 * b * b + e] = 0.0;
             __syncthreads();
             continue;
         }
-        // V by tile columns j descending; S_a = sum_{b > a} V_b W_ab^T gathers
-        // in pu, one term per step in a fixed order, and V_{jt-1} = -S_{jt-1}
-        // is finished by the wavefront adding the last term
-        for (int jt = T - 1; jt >= 1; --jt) {
-#pragma unroll
-            for (int s = 0; s < RR_SLOTS; ++s) {
-                const int v = slot_word(ab[s]);
-                const int a = v >> 8, bt = v & 255;
-                if (v >= 0 && bt == jt && a < jt) {
-                    v4d acc;
-                    if (jt == T - 1) {
-                        acc = t[s];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) acc[q] = pu[a * 256 + 64 * q + lane];
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            acc = mfma16(vv[jt * 256 + j * 16 + 4 * q + g], t[s][q], acc);   // V_jt[j][4q+g]
-                    }
-                    if (a == jt - 1) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) vv[a * 256 + 64 * q + lane] = -acc[q];
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) pu[a * 256 + 64 * q + lane] = acc[q];
-                    }
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            __syncthreads();
-        }
-        // X V by tile columns (V_{T-1} = I)
+        // X V by tile columns (V_{T-1} = I), X = R_{T-1}^{-1}
+        const double* xl = dinv + ((T - 1) & 1) * 256;
         for (int a = w; a < T; a += RR_WAVES) {
             v4d y = {0.0, 0.0, 0.0, 0.0};
             if (a == T - 1) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) y[q] = dinv[64 * q + lane];
+                for (int q = 0; q < 4; ++q) y[q] = xl[64 * q + lane];
             } else {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) y = mfma16(dinv[j * 16 + 4 * q + g], vv[a * 256 + 64 * q + lane], y);
+                for (int q = 0; q < 4; ++q) y = mfma16(xl[j * 16 + 4 * q + g], vv[a * 256 + 64 * q + lane], y);
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) vv[a * 256 + 64 * q + lane] = y[q];
