@@ -730,7 +730,8 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
     __shared__ double pw[2 * PANEL];
     __shared__ double dg[PANEL];        // the diagonal tiles U_aa
     __shared__ double dinv[2 * 256];    // D_a^{-1} in buffer a & 1; X = R_{T-1}^{-1} for a = T - 1
-    __shared__ int sh_flag, f_dinv, f_wcrit, f_diag;
+    __shared__ int sh_flag, f_dinv, f_wcrit, f_diag, v_done;
+    __shared__ int s_next[RR_TMAX];
     __shared__ int64_t sh_next;
     int* idx = reinterpret_cast<int*>(pw + PANEL);
     double* vv = pw;
@@ -794,26 +795,39 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
         if (tid == 0) {
             sh_flag = 1;
             f_dinv = f_wcrit = f_diag = -1;
+            v_done = T - 1;
+            for (int a = 0; a < T; ++a) s_next[a] = T - 1;
         }
         __syncthreads();
         // Element (4q + g, j) of tile U_ab is Kpad[16 a + 4q + g][16 b + j].
         // Each element is one load straight into its register, from A or, for
         // a missing block, a padding entry or an unused slot, from the
-        // constants {0, 1}: no branches and nothing to do after the loads,
-        // so all of them are in flight together.
-        auto tile_load = [&](int a, int bt, bool use, v4d& t) {
+        // constants {0, 1}: no branches and nothing to do after the loads.
+        // fill_map looks up the block map for a tile's 4 elements (clamped
+        // positions are in range), fill_load issues its loads; the callers
+        // run the lookups of several tiles before their loads, so that the
+        // LDS latency is paid once per group and the loads overlap.
+        auto fill_map = [&](int a, int bt, int (&e)[4]) {
+            const int pcc = max(16 * bt + j - pad, 0);
+            const int y = (pcc * bmul) >> 16;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int prc = max(16 * a + 4 * q + g - pad, 0);
+                e[q] = idx[((prc * bmul) >> 16) * m + y];
+            }
+        };
+        auto fill_load = [&](int a, int bt, bool use, const int (&e)[4], v4d& t) {
             const int pc = 16 * bt + j - pad;
             const int pcc = max(pc, 0);
-            const int y = (pcc * bmul) >> 16, ry = pcc - y * b;
+            const int ry = pcc - ((pcc * bmul) >> 16) * b;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int pr = 16 * a + 4 * q + g - pad;
                 const int prc = max(pr, 0);
-                const int x = (prc * bmul) >> 16, rx = prc - x * b;
-                const int e = idx[x * m + y];   // clamped positions are in range
+                const int rx = prc - ((prc * bmul) >> 16) * b;
                 const bool real = pr >= 0 && pc >= 0;
-                const double* src = use && real && e >= 0
-                                        ? a_vals + ((int64_t)e * b * b + rx * b + ry)
+                const double* src = use && real && e[q] >= 0
+                                        ? a_vals + ((int64_t)e[q] * b * b + rx * b + ry)
                                         : rr_zero_one + ((use && !real && pr == pc) ? 1 : 0);
                 t[q] = *src;
             }
@@ -852,9 +866,20 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
             }
         };
         auto publish = [&](int* f, int v) { __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP); };
+        auto wait_le = [&](int* f, int v) {   // bounded, for the decreasing counter of finished V tiles
+            for (int spin = 0; __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) > v; ++spin) {
+                if (spin > (1 << 14)) {
+                    if (lane == 0) sh_flag = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        };
         for (int a = w; a < T; a += RR_WAVES) {
+            int e[4];
             v4d d;
-            tile_load(a, a, true, d);
+            fill_map(a, a, e);
+            fill_load(a, a, true, e, d);
 #pragma unroll
             for (int q = 0; q < 4; ++q) dg[a * 256 + 64 * q + lane] = d[q];
         }
@@ -904,7 +929,21 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
             }
             ok_row = sh_flag != 0;
             if (ok_row) {
-                for (int jt = T - 1; jt >= 1; --jt) __syncthreads();   // the back-substitution's barriers
+                // Y_a = X V_a as soon as V_a is out (V_{T-1} = I), to dg
+                const double* xl = dinv + ((T - 1) & 1) * 256;   // X = R_{T-1}^{-1}
+                for (int a = T - 1; a >= 0; --a) {
+                    v4d y = {0.0, 0.0, 0.0, 0.0};
+                    if (a == T - 1) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) y[q] = xl[64 * q + lane];
+                    } else {
+                        wait_le(&v_done, a);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) y = mfma16(xl[j * 16 + 4 * q + g], vv[a * 256 + 64 * q + lane], y);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) dg[a * 256 + 64 * q + lane] = y[q];
+                }
             }
         } else {
             // ------------------------------------------------------ the tiles
@@ -924,10 +963,22 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
                 }
             }
             v4d t[RR_SLOTS];
+            constexpr int FG = 5;   // slots per fill group
+            static_assert(RR_SLOTS % FG == 0, "fill groups");
 #pragma unroll
-            for (int s = 0; s < RR_SLOTS; ++s) {
-                const bool use = ab[s] >= 0;   // unused slots read zeros through tile (0, 0)
-                tile_load(use ? ab[s] >> 8 : 0, use ? ab[s] & 255 : 0, use, t[s]);
+            for (int s0 = 0; s0 < RR_SLOTS; s0 += FG) {
+                int e[FG][4];
+#pragma unroll
+                for (int s = s0; s < s0 + FG; ++s) {   // unused slots read zeros through tile (0, 0)
+                    const bool use = ab[s] >= 0;
+                    fill_map(use ? ab[s] >> 8 : 0, use ? ab[s] & 255 : 0, e[s - s0]);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int s = s0; s < s0 + FG; ++s) {
+                    const bool use = ab[s] >= 0;
+                    fill_load(use ? ab[s] >> 8 : 0, use ? ab[s] & 255 : 0, use, e[s - s0], t[s]);
+                }
             }
             __syncthreads();
             for (int c = -1; c + 1 < T; ++c) {
@@ -964,6 +1015,7 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
                         pa[q] = puc[a * 256 + 64 * q + lane];    // -U_ca^T[j][4q+g]
                         pb[q] = pwc[bt * 256 + 64 * q + lane];   // W_cb[4q+g][j]
                     }
+                    __builtin_amdgcn_sched_barrier(0);   // all 8 operands in flight together
 #pragma unroll
                     for (int q = 0; q < 4; ++q) tt = mfma16(pa[q], pb[q], tt);
                 };
@@ -1025,10 +1077,12 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
             // address tiles by slot, so values gone bad are harmless
             ok_row = sh_flag != 0;
             if (ok_row) {
-                // V by tile columns jt descending; S_a = sum_{b > a} V_b W_ab^T
-                // gathers in pu, one term per step in a fixed order, and
-                // V_{jt-1} = -S_{jt-1} is finished by the wavefront adding the
-                // last term
+                // V_{T-1} = I, V_a = -S_a with S_a = sum_{b > a} V_b W_ab^T, as a
+                // dataflow: each tile (a, b), by b descending, waits for V_b
+                // (v_done <= b) and for row a's sum to hold the terms above b
+                // (s_next[a] == b), adds its term in pu (a fixed order) and
+                // publishes; the tile (a, a + 1) finishes V_a. Every wait is on
+                // a tile of larger b, so the waits end.
                 for (int jt = T - 1; jt >= 1; --jt) {
 #pragma unroll
                     for (int s = 0; s < RR_SLOTS; ++s) {
@@ -1039,6 +1093,8 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
                             if (jt == T - 1) {
                                 acc = t[s];
                             } else {
+                                wait_le(&v_done, jt);
+                                wait_eq(&s_next[a], jt);
 #pragma unroll
                                 for (int q = 0; q < 4; ++q) acc[q] = pu[a * 256 + 64 * q + lane];
 #pragma unroll
@@ -1048,16 +1104,21 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
                             if (a == jt - 1) {
 #pragma unroll
                                 for (int q = 0; q < 4; ++q) vv[a * 256 + 64 * q + lane] = -acc[q];
+                                publish(&v_done, a);
                             } else {
 #pragma unroll
                                 for (int q = 0; q < 4; ++q) pu[a * 256 + 64 * q + lane] = acc[q];
+                                publish(&s_next[a], jt - 1);
                             }
                         }
                         __builtin_amdgcn_sched_barrier(0);
                     }
-                    __syncthreads();
                 }
             }
+        }
+        if (ok_row) {
+            __syncthreads();
+            ok_row = sh_flag != 0;   // a wait of the back-substitution that ran out
         }
         if (!ok_row) {
             if (tid == 0) atomicMin(bad_row, (int)k);
@@ -1065,28 +1126,13 @@ __global__ __launch_bounds__(RR_NT) void k_fsai_setup_rr(int64_t nrows, const in
             __syncthreads();
             continue;
         }
-        // X V by tile columns (V_{T-1} = I), X = R_{T-1}^{-1}
-        const double* xl = dinv + ((T - 1) & 1) * 256;
-        for (int a = w; a < T; a += RR_WAVES) {
-            v4d y = {0.0, 0.0, 0.0, 0.0};
-            if (a == T - 1) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) y[q] = xl[64 * q + lane];
-            } else {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) y = mfma16(xl[j * 16 + 4 * q + g], vv[a * 256 + 64 * q + lane], y);
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) vv[a * 256 + 64 * q + lane] = y[q];
-        }
-        __syncthreads();
         // G_k[t][x b + cc] = row 16 - b + t of the last tile row, column pad + x b + cc
         const int bb = b * b;
         for (int e = tid; e < m * bb; e += RR_NT) {
             const int x = e / bb, rem = e - x * bb;
             const int tr = rem / b, cc = rem - tr * b;
             const int p = pad + x * b + cc;
-            g_vals[(p0 + x) * bb + rem] = vv[(p >> 4) * 256 + (16 - b + tr) * 16 + (p & 15)];
+            g_vals[(p0 + x) * bb + rem] = dg[(p >> 4) * 256 + (16 - b + tr) * 16 + (p & 15)];
         }
         __syncthreads();
     }
