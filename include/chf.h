@@ -23,15 +23,15 @@
  *
  * Tuning overrides, read from the environment (results stay within the
  * parity bounds of every setting; they exist for tests and measurement):
- *  - CHF_FSAI_CONFIG="<width>,<tile threshold>": the local solver of
- *    chf_fsai_setup (width 64, 128 or 256; rows wider than the threshold use
- *    the tiled MFMA solver, 0 = never) instead of the autotuned choice.
+ *  - CHF_FSAI_CONFIG="<width>,<tile threshold>[,<rr threshold>]": the local
+ *    solver of chf_fsai_setup (width 64, 128 or 256; rows wider than the tile
+ *    threshold use the tiled MFMA solver, 0 = never; local systems wider than
+ *    the rr threshold, up to 240, use the register-resident MFMA kernel,
+ *    absent = never) instead of the autotuned choice.
  *  - CHF_SPMV_SPLIT_BELOW=<slices>: SpMV layouts with fewer slices use one
  *    workgroup per slice (default 2048; 0 = never).
  *  - CHF_SPMV_NONTEMPORAL=0: plain instead of non-temporal matrix loads
  *    (read once per process).
- *  - CHF_ADAPTIVE_PLACEMENT=global|v|all: where Algorithm 1 keeps A[P,P]^{-1}
- *    and V (global slot or LDS) instead of the automatic choice.
  */
 #ifndef CHF_H
 #define CHF_H

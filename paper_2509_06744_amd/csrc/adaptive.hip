@@ -318,19 +318,26 @@ struct AiState {
     int* nze;       // cap x AD_MAXP
 };
 
-__host__ __device__ inline int64_t ai_global_doubles(int Mmax, int b, int cap, bool kinv_g, bool v_g) {
+__host__ __device__ inline int64_t ai_global_doubles(int Mmax, int b, int cap) {
     const int64_t ints = (int64_t)cap * (3 + 2 * AD_MAXP);
-    return (kinv_g ? ai_tri(Mmax) : 0) + (v_g ? 2 * (int64_t)Mmax * b : 0) + 2 * (int64_t)cap * b * b + cap +
-           (ints + 1) / 2;
+    return ai_tri(Mmax) + 2 * (int64_t)Mmax * b + 2 * (int64_t)cap * b * b + cap + (ints + 1) / 2;
 }
 
 __host__ __device__ inline int64_t ai_small_doubles(int b) { return 5 * (int64_t)b * b + 2 * b; }
 __host__ __device__ inline int64_t ai_group_doubles(int b) { return 3 * (int64_t)b * b + 3 * b; }
 
-__host__ __device__ inline int64_t ai_lds_doubles(int Mmax, int b, int maxrow, bool kinv_l, bool v_l) {
+__host__ __device__ inline int64_t ai_lds_doubles(int b, int maxrow) {
     const int NB = 64 / b;
-    return ai_small_doubles(b) + (int64_t)NB * ai_group_doubles(b) + (maxrow + 1) / 2 + (kinv_l ? ai_tri(Mmax) : 0) +
-           (v_l ? 2 * (int64_t)Mmax * b : 0);
+    return ai_small_doubles(b) + (int64_t)NB * ai_group_doubles(b) + (maxrow + 1) / 2;
+}
+
+// threadIdx.x behind an empty asm: values derived from it are formed where a
+// phase uses them instead of being hoisted out of the row and step loops,
+// which would keep every phase's lane addresses live through all the others.
+__device__ __forceinline__ int ai_lane() {
+    int l = threadIdx.x;
+    asm volatile("" : "+v"(l));
+    return l;
 }
 
 // Cholesky of a b x b SPD matrix held row-major in LDS (Mx) by the b lanes of
@@ -373,7 +380,7 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
                                          const double* LSinv, const double* U, const double* LH,
                                          const double* LHrd, double* gbufs, int* flag) {
     if (BC > 0) b = BC;
-    const int lane = threadIdx.x;
+    const int lane = ai_lane();
     const int bb = b * b;
     const int ci = lane / b, r = lane - ci * b;
     const bool act = ci < cnt;
@@ -405,40 +412,49 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
         }
         // E_c -= V_j^T A_jc over the blocks j of P~ next to c; each V_j block
         // (b x b) is staged through the group's LDS buffer by rows (the trip
-        // count is made uniform across the wavefront for the barriers)
+        // count is made uniform across the wavefront for the barriers). Lane r
+        // issues the loads of row r of V_j and column r of A_jc together.
         int nmax = act ? nn : 0;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
-        // lane r of a group holds list entry r (one load for the first b entries)
+        // lane r of a group holds list entry r of the current chunk of b entries
         const int g0l = lane - r;
         int my_pos = 0, my_ea = 0;
-        if (act && r < nn) {
-            my_pos = S.nzp[(int64_t)slot * AD_MAXP + r];
-            my_ea = S.nze[(int64_t)slot * AD_MAXP + r];
-        }
 #pragma unroll 1
         for (int t = 0; t < nmax; ++t) {
-            const bool live = act && t < nn;
-            int pos = __shfl(my_pos, g0l + min(t, b - 1), 64);
-            int ea = __shfl(my_ea, g0l + min(t, b - 1), 64);
-            if (live && t >= b) {
-                pos = S.nzp[(int64_t)slot * AD_MAXP + t];
-                ea = S.nze[(int64_t)slot * AD_MAXP + t];
+            if (t % b == 0) {
+                my_pos = my_ea = 0;
+                if (act && t + r < nn) {
+                    my_pos = S.nzp[(int64_t)slot * AD_MAXP + t + r];
+                    my_ea = S.nze[(int64_t)slot * AD_MAXP + t + r];
+                }
             }
+            const int pos = __shfl(my_pos, g0l + t % b, 64);
+            const int ea = __shfl(my_ea, g0l + t % b, 64);
+            const bool live = act && t < nn;
+            double vr[MAXB], ac[MAXB];
             if (live) {
-                const double* vr = V + (int64_t)(pos * b + r) * b;
+                const double* vp = V + (int64_t)(pos * b + r) * b;
+                const double* ap = a_vals + (int64_t)ea * bb + r;
+#pragma unroll
+                for (int i = 0; i < MAXB; ++i)
+                    if (i < b) {
+                        vr[i] = vp[i];
+                        ac[i] = ap[i * b];
+                    }
 #pragma unroll
                 for (int i = 0; i < MAXB; ++i)
                     if (i < b) BX[r * b + i] = vr[i];
             }
             __syncthreads();
             if (live) {
-                for (int q = 0; q < b; ++q) {
-                    const double aq = a_vals[(int64_t)ea * bb + q * b + r];
 #pragma unroll
-                    for (int i = 0; i < MAXB; ++i)
-                        if (i < b) e[i] -= BX[q * b + i] * aq;
-                }
+                for (int q = 0; q < MAXB; ++q)
+                    if (q < b) {
+#pragma unroll
+                        for (int i = 0; i < MAXB; ++i)
+                            if (i < b) e[i] -= BX[q * b + i] * ac[q];
+                    }
             }
             __syncthreads();
         }
@@ -561,7 +577,7 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
 __device__ inline void ai_init_slots(int k, int b, int s0, int s1, const int* __restrict__ a_rowptr,
                                      const int* __restrict__ a_col, const double* __restrict__ a_vals,
                                      const AiState& S, int* tmp_a, int* tmp_b) {
-    const int lane = threadIdx.x;
+    const int lane = ai_lane();
     const int bb = b * b;
 #pragma unroll 1
     for (int c0 = s0; c0 < s1; c0 += 64) {
@@ -659,6 +675,8 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
     const int total = nforced + tmax;
     #pragma unroll 1
     for (int step = 0; step < total && sh[3]; ++step) {
+        const int lane = ai_lane(), r = lane;
+        const bool g0 = lane < b;
         const bool is_forced = step < nforced;
         if (ncand == 0 && !is_forced) break;
         #pragma unroll 1
@@ -771,35 +789,70 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
             group_chol(LH, LHrd, gbufs, b, r, g0, okH);
             if (g0 && !okH) sh[3] = 0;
         }
-        // V = Kinv A[P~, c*] (c*'s list holds its nonzero blocks A_jc*)
+        // V = Kinv A[P~, c*] (c*'s list holds its nonzero blocks A_jc*) and
+        // Vt = V L_S^{-T}, one row i of both per lane. c*'s blocks A_jc* are
+        // staged in LDS (the group buffers are free here) in chunks of list
+        // entries; a lane's Kinv elements of an entry are loaded together.
         {
             const int nn = S.nzn[bs];
-            #pragma unroll 1
-            for (int idx = lane; idx < M * b; idx += 64) {
-                const int i = idx / b, s = idx - i * b;
-                double acc = 0.0;
-                #pragma unroll 1
-                for (int t = 0; t < nn; ++t) {
-                    const int pos = S.nzp[(int64_t)bs * AD_MAXP + t];
-                    const int ea = S.nze[(int64_t)bs * AD_MAXP + t];
-                                        for (int q = 0; q < b; ++q)
-                        acc += S.kinv[kidx(i, pos * b + q)] * a_vals[(int64_t)ea * bb + q * b + s];
+            if (lane < nn) {
+                tmp_a[lane] = S.nzp[(int64_t)bs * AD_MAXP + lane];
+                tmp_b[lane] = S.nze[(int64_t)bs * AD_MAXP + lane];
+            }
+            const int ln = ai_lane();
+            const int per = (int)((NB * ai_group_doubles(b)) / bb);   // entries per chunk
+#pragma unroll 1
+            for (int i0 = 0; i0 < M; i0 += 64) {
+                const int i = i0 + ln;
+                const bool live = i < M;
+                double acc[MAXB];
+#pragma unroll
+                for (int s2 = 0; s2 < MAXB; ++s2) acc[s2] = 0.0;
+#pragma unroll 1
+                for (int t0 = 0; t0 < nn; t0 += per) {
+                    const int t1 = min(nn, t0 + per);
+                    __syncthreads();
+#pragma unroll 1
+                    for (int e = ln; e < (t1 - t0) * bb; e += 64) {
+                        const int tt = e / bb;
+                        gbufs[e] = a_vals[(int64_t)tmp_b[t0 + tt] * bb + (e - tt * bb)];
+                    }
+                    __syncthreads();
+#pragma unroll 1
+                    for (int t = t0; t < t1; ++t) {
+                        const int pos = tmp_a[t];
+                        const double* at = gbufs + (t - t0) * bb;
+                        double kc[MAXB];
+#pragma unroll
+                        for (int q = 0; q < MAXB; ++q)
+                            if (q < b) kc[q] = live ? S.kinv[kidx(i, pos * b + q)] : 0.0;
+#pragma unroll
+                        for (int q = 0; q < MAXB; ++q)
+                            if (q < b) {
+#pragma unroll
+                                for (int s2 = 0; s2 < MAXB; ++s2)
+                                    if (s2 < b) acc[s2] += kc[q] * at[q * b + s2];
+                            }
+                    }
                 }
-                S.V[idx] = acc;
+                if (live) {
+#pragma unroll
+                    for (int s2 = 0; s2 < MAXB; ++s2)
+                        if (s2 < b) {
+                            S.V[(int64_t)i * b + s2] = acc[s2];
+                            double vt = 0.0;
+#pragma unroll
+                            for (int q = 0; q < MAXB; ++q)
+                                if (q < b && q <= s2) vt += acc[q] * LSinv[s2 * b + q];
+                            S.Vt[(int64_t)i * b + s2] = vt;
+                        }
+                }
             }
         }
         __syncthreads();
         if (!sh[3]) {
             if (lane == 0) atomicMin(err, k);
             break;
-        }
-        // Vt = V L_S^{-T}
-        #pragma unroll 1
-        for (int idx = lane; idx < M * b; idx += 64) {
-            const int i = idx / b, s = idx - i * b;
-            double acc = 0.0;
-                        for (int q = 0; q <= s; ++q) acc += S.V[(int64_t)i * b + q] * LSinv[s * b + q];
-            S.Vt[idx] = acc;
         }
         // candidate list: drop c* (the last slot moves into its place)
         const int last = ncand - 1;
@@ -831,32 +884,104 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
             S.ecs[q] = e;
             if (e >= 0) mark[e - r0] = 1;
         }
-        // Kinv <- bordered inverse (packed rows keep their offsets as M grows)
+        // Kinv <- bordered inverse (packed rows keep their offsets as M grows).
+        // Rows i < M: Kinv_ij += Vt_i . Vt_j; each lane walks its elements
+        // with (i, j) advanced incrementally and the next element's operands
+        // loaded while one is formed.
         {
-            const int64_t tot = ai_tri(M + b);
+            const int64_t top = ai_tri(M);
+            const int ln = ai_lane();
+            int i = 0, j = ln;
+            while (j > i) {
+                j -= i + 1;
+                ++i;
+            }
+            // compile-time block sizes up to 10: two elements (idx and idx + 64)
+            // per pass and the border rows unrolled; otherwise one element per
+            // pass (register budget). Each element's loads are issued together.
+            constexpr bool wide = !(BC > 0 && MAXB <= 10);
+            constexpr int KE = wide ? 1 : 2;
 #pragma unroll 1
-            for (int64_t idx = lane; idx < tot; idx += 64) {
-                int i = (int)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
-                while (ai_tri(i + 1) <= idx) ++i;
-                while (ai_tri(i) > idx) --i;
-                const int j = (int)(idx - ai_tri(i));
-                double v;
-                if (i < M) {
-                    double acc = 0.0;
-                    for (int q = 0; q < b; ++q) acc += S.Vt[(int64_t)i * b + q] * S.Vt[(int64_t)j * b + q];
-                    v = S.kinv[idx] + acc;
-                } else {
-                    const int rr = i - M;
-                    double acc = 0.0;
-                    if (j < M) {
-                        for (int q = rr; q < b; ++q) acc -= LSinv[q * b + rr] * S.Vt[(int64_t)j * b + q];
-                    } else {
-                        const int ss = j - M;
-                        for (int q = rr; q < b; ++q) acc += LSinv[q * b + rr] * LSinv[q * b + ss];
+            for (int64_t idx = ln; idx < top; idx += 64 * KE) {
+                int ie[KE], je[KE];
+                ie[0] = i;
+                je[0] = j;
+#pragma unroll
+                for (int u = 1; u < KE; ++u) {
+                    ie[u] = ie[u - 1];
+                    je[u] = je[u - 1] + 64;
+                    while (je[u] > ie[u]) {
+                        je[u] -= ie[u] + 1;
+                        ++ie[u];
                     }
-                    v = acc;
                 }
-                S.kinv[idx] = v;
+                double vi[KE][MAXB], vj[KE][MAXB], kk[KE];
+#pragma unroll
+                for (int u = 0; u < KE; ++u) {
+                    const bool in = idx + 64 * u < top;
+#pragma unroll
+                    for (int q = 0; q < MAXB; ++q)
+                        if (q < b) {
+                            vi[u][q] = in ? S.Vt[(int64_t)ie[u] * b + q] : 0.0;
+                            vj[u][q] = in ? S.Vt[(int64_t)je[u] * b + q] : 0.0;
+                        }
+                    kk[u] = in ? S.kinv[idx + 64 * u] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < KE; ++u) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < MAXB; ++q)
+                        if (q < b) acc += vi[u][q] * vj[u][q];
+                    if (idx + 64 * u < top) S.kinv[idx + 64 * u] = kk[u] + acc;
+                }
+                i = ie[KE - 1];
+                j = je[KE - 1] + 64;
+                while (j > i) {
+                    j -= i + 1;
+                    ++i;
+                }
+            }
+            // border rows i = M + rr, columns j < M: -(L_S^{-T} Vt_j^T)_rr,
+            // one lane per column
+#pragma unroll 1
+            for (int jj = ln; jj < M; jj += 64) {
+                double vr[MAXB];
+#pragma unroll
+                for (int q = 0; q < MAXB; ++q)
+                    if (q < b) vr[q] = S.Vt[(int64_t)jj * b + q];
+                if constexpr (!wide) {
+#pragma unroll
+                    for (int rr = 0; rr < MAXB; ++rr)
+                        if (rr < b) {
+                            double acc = 0.0;
+#pragma unroll
+                            for (int q = 0; q < MAXB; ++q)
+                                if (q < b && q >= rr) acc -= LSinv[q * b + rr] * vr[q];
+                            S.kinv[ai_tri(M + rr) + jj] = acc;
+                        }
+                } else {
+#pragma unroll 1
+                    for (int rr = 0; rr < b; ++rr) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int q = 0; q < MAXB; ++q)
+                            if (q < b && q >= rr) acc -= LSinv[q * b + rr] * vr[q];
+                        S.kinv[ai_tri(M + rr) + jj] = acc;
+                    }
+                }
+            }
+            // corner: L_S^{-T} L_S^{-1}, lower part
+#pragma unroll 1
+            for (int e = lane; e < (b * (b + 1)) / 2; e += 64) {
+                int rr = 0, ss = e;
+                while (ss > rr) {
+                    ss -= rr + 1;
+                    ++rr;
+                }
+                double acc = 0.0;
+                for (int q = rr; q < b; ++q) acc += LSinv[q * b + rr] * LSinv[q * b + ss];
+                S.kinv[ai_tri(M + rr) + M + ss] = acc;
             }
         }
         __syncthreads();
@@ -918,13 +1043,13 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
 }
 
 template <int MAXB, int BC>
-__global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, double thresh, int cap,
+__device__ __forceinline__ void ai_kernel(int64_t nb, int b, int tmax, double thresh, int cap,
                                                  const int* __restrict__ a_rowptr, const int* __restrict__ a_col,
                                                  const double* __restrict__ a_vals, const int* __restrict__ p0_rowptr,
                                                  const int* __restrict__ p0_col, int out_stride,
                                                  int* __restrict__ out_cols,
-                                                 int* __restrict__ out_cnt, int kinv_lds, int v_lds, int Mmax,
-                                                 int maxrow, double* scratch, int64_t gstride, int* counter,
+                                                 int* __restrict__ out_cnt, int Mmax, double* scratch,
+                                                 int64_t gstride, int* counter,
                                                  int* err) {
     if (BC > 0) b = BC;
     extern __shared__ double lds[];
@@ -937,25 +1062,13 @@ __global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, do
     double* sm = lds;
     double* gbufs = sm + ai_small_doubles(b);
     int* mark = reinterpret_cast<int*>(gbufs + NB * ai_group_doubles(b));
-    double* lfree = gbufs + NB * ai_group_doubles(b) + (maxrow + 1) / 2;
+    // the row's state lives in the workgroup's global slot
     double* g = scratch + (int64_t)blockIdx.x * gstride;
     AiState S;
-    if (kinv_lds) {
-        S.kinv = lfree;
-        lfree += ai_tri(Mmax);
-    } else {
-        S.kinv = g;
-        g += ai_tri(Mmax);
-    }
-    if (v_lds) {
-        S.V = lfree;
-        S.Vt = lfree + (int64_t)Mmax * b;
-    } else {
-        S.V = g;
-        S.Vt = g + (int64_t)Mmax * b;
-        g += 2 * (int64_t)Mmax * b;
-    }
-    S.W = g;
+    S.kinv = g;
+    S.V = g + ai_tri(Mmax);
+    S.Vt = S.V + (int64_t)Mmax * b;
+    S.W = S.Vt + (int64_t)Mmax * b;
     S.H = S.W + (int64_t)cap * bb;
     S.gain = S.H + (int64_t)cap * bb;
     int* gi = reinterpret_cast<int*>(S.gain + cap);
@@ -975,17 +1088,40 @@ __global__ __launch_bounds__(64) void k_adaptive(int64_t nb, int b, int tmax, do
     }
 }
 
+// Block sizes up to 4, and 10 (compile-time), run two wavefronts per SIMD;
+// the others take the registers they need.
+#define CHF_AI_PARAMS                                                                                        \
+    int64_t nb, int b, int tmax, double thresh, int cap, const int* __restrict__ a_rowptr,                   \
+        const int* __restrict__ a_col, const double* __restrict__ a_vals, const int* __restrict__ p0_rowptr, \
+        const int* __restrict__ p0_col, int out_stride, int* __restrict__ out_cols, int* __restrict__ out_cnt,   \
+        int Mmax, double* scratch, int64_t gstride, int* counter, int* err
+#define CHF_AI_ARGS \
+    nb, b, tmax, thresh, cap, a_rowptr, a_col, a_vals, p0_rowptr, p0_col, out_stride, out_cols, out_cnt, Mmax, \
+        scratch, gstride, counter, err
+template <int MAXB, int BC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_adaptive(CHF_AI_PARAMS) {
+    ai_kernel<MAXB, BC>(CHF_AI_ARGS);
+}
+template <int MAXB, int BC>
+__global__ __launch_bounds__(64) void k_adaptive_wide(CHF_AI_PARAMS) {
+    ai_kernel<MAXB, BC>(CHF_AI_ARGS);
+}
+#undef CHF_AI_PARAMS
+#undef CHF_AI_ARGS
+
 template <int MAXB, int BC>
 static void ai_launch(int64_t grid, size_t dyn, hipStream_t s, int64_t nb, int b, int tmax, double thresh, int cap,
                       chf_bsr A, const int* p0_rowptr, const int* p0_col, int out_stride, int* out_cols, int* out_cnt,
-                      int kinv_lds, int v_lds, int Mmax, int maxrow, double* scratch, int64_t stride, int* counter,
-                      int* err) {
-    auto kern = k_adaptive<MAXB, BC>;
+                      int Mmax, double* scratch, int64_t stride, int* counter, int* err) {
+    void (*kern)(int64_t, int, int, double, int, const int*, const int*, const double*, const int*, const int*, int,
+                 int*, int*, int, double*, int64_t, int*, int*);
+    if constexpr (MAXB <= 4 || (BC > 0 && MAXB <= 10)) kern = k_adaptive<MAXB, BC>;
+    else kern = k_adaptive_wide<MAXB, BC>;
     if (dyn > 64 * 1024)
         CHF_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(64), dyn, s, nb, b, tmax, thresh, cap,
                        A->d_rowptr.p, A->d_colidx.p, A->d_vals.p, p0_rowptr, p0_col, out_stride, out_cols, out_cnt,
-                       kinv_lds, v_lds, Mmax, maxrow, scratch, stride, counter, err);
+                       Mmax, scratch, stride, counter, err);
     CHF_LAUNCH_CHECK();
 }
 
@@ -1038,38 +1174,25 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, const chf_pattern_s* P0, int tma
     CHF_HIP(hipGetDevice(&dev));
     CHF_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     const size_t static_lds = AD_MAXP * 4 + 8 * 4 + 64 + 2 * 64 * 4;
-    // placement: the per-candidate state always lives in the workgroup's
-    // global slot; Kinv and V / Vt move to LDS only while 8 workgroups still
-    // fit on a CU (one wavefront each: occupancy hides the latency of the
-    // short dependent steps)
-    auto lds_for = [&](bool kl, bool vl) { return (size_t)ai_lds_doubles(Mmax, b, (int)maxrow, kl, vl) * 8; };
-    const size_t budget = (size_t)lim / 8 > static_lds ? (size_t)lim / 8 - static_lds : 0;
-    bool kinv_lds = lds_for(true, true) <= budget;
-    bool v_lds = kinv_lds || lds_for(false, true) <= budget;
-    if (const char* env = std::getenv("CHF_ADAPTIVE_PLACEMENT")) {   // tuning knob: "global", "v", "all"
-        const std::string p(env);
-        if (p == "global") kinv_lds = v_lds = false;
-        if (p == "v") { kinv_lds = false; v_lds = true; }
-        if (p == "all") kinv_lds = v_lds = true;
-    }
-    const size_t dyn = lds_for(kinv_lds, v_lds);
+    // the row's state (Kinv, V, Vt and the candidates) lives in the
+    // workgroup's global slot; LDS holds the b x b work buffers
+    const size_t dyn = (size_t)ai_lds_doubles(b, (int)maxrow) * 8;
     CHF_CHECK(dyn + static_lds <= (size_t)lim, CHF_EINVAL, "adaptive pattern: block size too large for LDS");
     const int cus = device_cu_count();
     const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / (dyn + static_lds + 512)));
     const int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, nb);
-    const int64_t stride = (ai_global_doubles(Mmax, b, cap, !kinv_lds, !v_lds) + 31) / 32 * 32;
+    const int64_t stride = (ai_global_doubles(Mmax, b, cap) + 31) / 32 * 32;
     DevBuf<double> scratch((size_t)grid * stride);
     DevBuf<int> out_cols((size_t)nb * width), out_cnt(nb), flags(2);
     int init[2] = {0, INT32_MAX};
     flags.upload(init, 2, s);
     const double thresh = -std::log(tau) + AD_GAIN_EPS;
-    const int ki = kinv_lds ? 1 : 0, vi = v_lds ? 1 : 0;
     // the block sizes of the workloads get their own instantiation (block
     // offsets are compile-time constants); others share one per size class
 #define CHF_AI_LAUNCH(MB, BCV)                                                                                   \
     ai_launch<MB, BCV>(grid, dyn, s, nb, b, tmax, thresh, cap, A, P0 ? d_p0_rowptr.p : nullptr,                  \
-                       P0 ? d_p0_col.p : nullptr, width, out_cols.p, out_cnt.p, ki, vi, Mmax, (int)maxrow,       \
-                       scratch.p, stride, flags.p, flags.p + 1)
+                       P0 ? d_p0_col.p : nullptr, width, out_cols.p, out_cnt.p, Mmax, scratch.p, stride, flags.p, \
+                       flags.p + 1)
     if (b == 10) CHF_AI_LAUNCH(10, 10);
     else if (b == 21) CHF_AI_LAUNCH(21, 21);
     else if (b <= 4) CHF_AI_LAUNCH(4, 0);
