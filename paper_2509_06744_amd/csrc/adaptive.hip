@@ -403,57 +403,89 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
     if (pending) {
         double et[MAXB], e[MAXB];
         int ecs = -1, nn = 0;
+        // lane r of a group holds list entry r (entries past b are loaded
+        // where they are used), loaded with the rest of the slot's state
+        int my_pos = 0, my_ea = 0;
         if (act) {
             ecs = S.ecs[slot];
+            nn = S.nzn[slot];
+            my_pos = S.nzp[(int64_t)slot * AD_MAXP + r];
+            my_ea = S.nze[(int64_t)slot * AD_MAXP + r];
 #pragma unroll
             for (int i = 0; i < MAXB; ++i)
                 if (i < b) e[i] = ecs >= 0 ? a_vals[(int64_t)ecs * bb + i * b + r] : 0.0;
-            nn = S.nzn[slot];
         }
-        // E_c -= V_j^T A_jc over the blocks j of P~ next to c; each V_j block
-        // (b x b) is staged through the group's LDS buffer by rows (the trip
-        // count is made uniform across the wavefront for the barriers). Lane r
-        // issues the loads of row r of V_j and column r of A_jc together.
+        // E_c -= V_j^T A_jc over the blocks j of P~ next to c, two list entries
+        // per pass: each V_j block (b x b) is staged through the group's LDS
+        // buffers by rows (the trip count is made uniform across the wavefront
+        // for the barriers); lane r loads row r of V_j and column r of A_jc,
+        // both entries' loads issued together
         int nmax = act ? nn : 0;
 #pragma unroll
         for (int o = 32; o >= 1; o >>= 1) nmax = max(nmax, __shfl_xor(nmax, o, 64));
-        // lane r of a group holds list entry r of the current chunk of b entries
         const int g0l = lane - r;
-        int my_pos = 0, my_ea = 0;
-#pragma unroll 1
-        for (int t = 0; t < nmax; ++t) {
-            if (t % b == 0) {
-                my_pos = my_ea = 0;
-                if (act && t + r < nn) {
-                    my_pos = S.nzp[(int64_t)slot * AD_MAXP + t + r];
-                    my_ea = S.nze[(int64_t)slot * AD_MAXP + t + r];
-                }
+        auto entry = [&](int t, int& pos, int& ea) {
+            pos = __shfl(my_pos, g0l + min(t, b - 1), 64);
+            ea = __shfl(my_ea, g0l + min(t, b - 1), 64);
+            if (t >= b && act && t < nn) {
+                pos = S.nzp[(int64_t)slot * AD_MAXP + t];
+                ea = S.nze[(int64_t)slot * AD_MAXP + t];
             }
-            const int pos = __shfl(my_pos, g0l + t % b, 64);
-            const int ea = __shfl(my_ea, g0l + t % b, 64);
-            const bool live = act && t < nn;
-            double vr[MAXB], ac[MAXB];
-            if (live) {
-                const double* vp = V + (int64_t)(pos * b + r) * b;
-                const double* ap = a_vals + (int64_t)ea * bb + r;
+        };
+#pragma unroll 1
+        for (int t = 0; t < nmax; t += 2) {
+            int pos0, ea0, pos1, ea1;
+            entry(t, pos0, ea0);
+            entry(t + 1, pos1, ea1);
+            const bool live0 = act && t < nn, live1 = act && t + 1 < nn;
+            double vr0[MAXB], ac0[MAXB], vr1[MAXB], ac1[MAXB];
+            if (live0) {
+                const double* vp = V + (int64_t)(pos0 * b + r) * b;
+                const double* ap = a_vals + (int64_t)ea0 * bb + r;
 #pragma unroll
                 for (int i = 0; i < MAXB; ++i)
                     if (i < b) {
-                        vr[i] = vp[i];
-                        ac[i] = ap[i * b];
+                        vr0[i] = vp[i];
+                        ac0[i] = ap[i * b];
                     }
+            }
+            if (live1) {
+                const double* vp = V + (int64_t)(pos1 * b + r) * b;
+                const double* ap = a_vals + (int64_t)ea1 * bb + r;
 #pragma unroll
                 for (int i = 0; i < MAXB; ++i)
-                    if (i < b) BX[r * b + i] = vr[i];
+                    if (i < b) {
+                        vr1[i] = vp[i];
+                        ac1[i] = ap[i * b];
+                    }
+            }
+            if (live0) {
+#pragma unroll
+                for (int i = 0; i < MAXB; ++i)
+                    if (i < b) BX[r * b + i] = vr0[i];
+            }
+            if (live1) {
+#pragma unroll
+                for (int i = 0; i < MAXB; ++i)
+                    if (i < b) BW[r * b + i] = vr1[i];
             }
             __syncthreads();
-            if (live) {
+            if (live0) {
 #pragma unroll
                 for (int q = 0; q < MAXB; ++q)
                     if (q < b) {
 #pragma unroll
                         for (int i = 0; i < MAXB; ++i)
-                            if (i < b) e[i] -= BX[q * b + i] * ac[q];
+                            if (i < b) e[i] -= BX[q * b + i] * ac0[q];
+                    }
+            }
+            if (live1) {
+#pragma unroll
+                for (int q = 0; q < MAXB; ++q)
+                    if (q < b) {
+#pragma unroll
+                        for (int i = 0; i < MAXB; ++i)
+                            if (i < b) e[i] -= BW[q * b + i] * ac1[q];
                     }
             }
             __syncthreads();
@@ -495,13 +527,45 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
         }
     }
     // L_W = chol(W_c); W_c is symmetric, so column r is row r
-    if (act) {
-#pragma unroll
-        for (int i = 0; i < MAXB; ++i)
-            if (i < b) BW[r * b + i] = w[i];
-    }
     bool ok = true;
-    group_chol(BW, rd, cb, b, r, act, ok);
+    const int g0l = lane - r;
+    if constexpr (BC > 0) {
+        // in registers: lane r keeps row r and takes the pivot column from the
+        // group by shuffles; the arithmetic is group_chol's, element by element
+        double rdv = 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q)
+            if (q < b) {
+                const double cr = w[q];
+                const double d = __shfl(cr, g0l + q, 64);
+                if (r >= q) ok = ok && d > 0.0 && isfinite(d);
+                const double sd = sqrt(fmax(d, 1e-300));
+                const double isd = 1.0 / sd;
+                const double lrq = cr * isd;
+                const double crs = lrq * isd;
+#pragma unroll
+                for (int j = q + 1; j < MAXB; ++j)
+                    if (j < b) {
+                        const double cj = __shfl(cr, g0l + j, 64);
+                        if (j <= r) w[j] -= crs * cj;
+                    }
+                if (r >= q) w[q] = r == q ? sd : lrq;
+                if (r == q) rdv = isd;
+            }
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i)
+                if (i < b) BW[r * b + i] = w[i];
+            rd[r] = rdv;
+        }
+    } else {
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i)
+                if (i < b) BW[r * b + i] = w[i];
+        }
+        group_chol(BW, rd, cb, b, r, act, ok);
+    }
     if (act) {
         // Z = L_H^{-1} H_kc, column r
         double z[MAXB];
@@ -532,8 +596,11 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
             }
     }
     __syncthreads();
+    // row r of N = X X^T, lower part (in registers for compile-time b)
+    double nrow[MAXB];
+#pragma unroll
+    for (int s = 0; s < MAXB; ++s) nrow[s] = 0.0;
     if (act) {
-        // row r of N = X X^T, lower part
         double xr[MAXB];
 #pragma unroll
         for (int q = 0; q < MAXB; ++q)
@@ -545,13 +612,32 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
 #pragma unroll
                 for (int q = 0; q < MAXB; ++q)
                     if (q < b) acc += xr[q] * BX[s * b + q];
-                B1[r * b + s] = acc;
+                if constexpr (BC > 0) nrow[s] = acc;
+                else B1[r * b + s] = acc;
             }
     }
     // -log det(I - N): Cholesky of I - N carried on N (the pivot of step q is
     // 1 - s_q with s_q the current N_qq, logged as log1p(-s_q)); every lane
     // sees every pivot and accumulates the sum itself
     double lg = 0.0;
+    if constexpr (BC > 0) {
+        // in registers, the pivot column by shuffles (same arithmetic)
+#pragma unroll
+        for (int q = 0; q < MAXB; ++q)
+            if (q < b) {
+                const double c0 = nrow[q];
+                const double sq = __shfl(c0, g0l + q, 64);
+                ok = ok && sq < 1.0;
+                lg += log1p(-sq);
+                const double cr = c0 / fmax(1.0 - sq, 1e-300);
+#pragma unroll
+                for (int j = q + 1; j < MAXB; ++j)
+                    if (j < b) {
+                        const double cj = __shfl(c0, g0l + j, 64);
+                        if (r > q && j <= r) nrow[j] += cr * cj;
+                    }
+            }
+    } else
 #pragma unroll 1
     for (int q = 0; q < b; ++q) {
         double* c = cb + (q & 1) * b;
