@@ -323,12 +323,18 @@ __host__ __device__ inline int64_t ai_global_doubles(int Mmax, int b, int cap) {
     return ai_tri(Mmax) + 2 * (int64_t)Mmax * b + 2 * (int64_t)cap * b * b + cap + (ints + 1) / 2;
 }
 
-__host__ __device__ inline int64_t ai_small_doubles(int b) { return 5 * (int64_t)b * b + 2 * b; }
-__host__ __device__ inline int64_t ai_group_doubles(int b) { return 3 * (int64_t)b * b + 3 * b; }
+// LDS: the row's b x b work matrices with the pivot buffers of group_chol,
+// then one buffer per group of b lanes (the group's own pivot buffers only
+// where its Cholesky factors run in LDS, i.e. for block sizes not fixed at
+// compile time).
+__host__ __device__ inline int64_t ai_small_doubles(int b) { return 5 * (int64_t)b * b + 4 * b; }
+__host__ __device__ inline int64_t ai_group_doubles(int b, bool reg) {
+    return 3 * (int64_t)b * b + (reg ? b : 3 * b);
+}
 
-__host__ __device__ inline int64_t ai_lds_doubles(int b, int maxrow) {
+__host__ __device__ inline int64_t ai_lds_doubles(int b, int maxrow, bool reg) {
     const int NB = 64 / b;
-    return ai_small_doubles(b) + (int64_t)NB * ai_group_doubles(b) + (maxrow + 1) / 2;
+    return ai_small_doubles(b) + (int64_t)NB * ai_group_doubles(b, reg) + (maxrow + 1) / 2;
 }
 
 // threadIdx.x behind an empty asm: values derived from it are formed where a
@@ -385,8 +391,8 @@ __device__ __forceinline__ void ai_batch(int k, int b, int s0, int cnt, bool pen
     const int ci = lane / b, r = lane - ci * b;
     const bool act = ci < cnt;
     const int slot = s0 + ci;
-    double* cb = gbufs + (act ? ci : 0) * ai_group_doubles(b);
-    double* rd = cb + 2 * b;   // 1 / diagonal of L_W
+    double* cb = gbufs + (act ? ci : 0) * ai_group_doubles(b, BC > 0);   // pivot buffers (LDS Cholesky)
+    double* rd = BC > 0 ? cb : cb + 2 * b;   // 1 / diagonal of L_W
     double* BW = rd + b;       // W_c by rows, then L_W
     double* B1 = BW + bb;      // e_c by columns, then Z by columns, then N by rows
     double* BX = B1 + bb;      // X by columns
@@ -708,6 +714,7 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
     double* U = LSinv + bb;
     double* LHrd = U + bb;      // 1 / diagonal of L_H
     double* LSrd = LHrd + b;    // 1 / diagonal of L_S
+    double* scb = LSrd + b;     // pivot buffers of the row's own factorisations
     const bool g0 = lane < b;   // group 0 does the single b x b factorisations
     const int r = lane;
     // H_kk = A_kk, L_H; candidates: A_kc != 0, c < k, with W_c = A_cc, H_kc = A_kc
@@ -743,7 +750,7 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
     if (g0)
 #pragma unroll 1
         for (int j = 0; j < b; ++j) LH[r * b + j] = Hkk[r * b + j];
-    group_chol(LH, LHrd, gbufs, b, r, g0, ok);
+    group_chol(LH, LHrd, scb, b, r, g0, ok);
     if (g0 && !ok) sh[3] = 0;
     __syncthreads();
     if (!sh[3]) {
@@ -830,7 +837,7 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
 #pragma unroll 1
                 for (int j = 0; j < b; ++j) LS[r * b + j] = S.W[(int64_t)bs * bb + j * b + r];
             bool okS = true;
-            group_chol(LS, LSrd, gbufs, b, r, g0, okS);
+            group_chol(LS, LSrd, scb, b, r, g0, okS);
             if (g0 && !okS) sh[3] = 0;
             if (g0) {
                 double x[MAXB], u[MAXB];
@@ -872,7 +879,7 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
 #pragma unroll 1
                 for (int j = 0; j < b; ++j) LH[r * b + j] = Hkk[r * b + j];
             bool okH = true;
-            group_chol(LH, LHrd, gbufs, b, r, g0, okH);
+            group_chol(LH, LHrd, scb, b, r, g0, okH);
             if (g0 && !okH) sh[3] = 0;
         }
         // V = Kinv A[P~, c*] (c*'s list holds its nonzero blocks A_jc*) and
@@ -886,7 +893,7 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
                 tmp_b[lane] = S.nze[(int64_t)bs * AD_MAXP + lane];
             }
             const int ln = ai_lane();
-            const int per = (int)((NB * ai_group_doubles(b)) / bb);   // entries per chunk
+            const int per = (int)((NB * ai_group_doubles(b, BC > 0)) / bb);   // entries per chunk
 #pragma unroll 1
             for (int i0 = 0; i0 < M; i0 += 64) {
                 const int i = i0 + ln;
@@ -1147,7 +1154,7 @@ __device__ __forceinline__ void ai_kernel(int64_t nb, int b, int tmax, double th
     const int NB = 64 / b;
     double* sm = lds;
     double* gbufs = sm + ai_small_doubles(b);
-    int* mark = reinterpret_cast<int*>(gbufs + NB * ai_group_doubles(b));
+    int* mark = reinterpret_cast<int*>(gbufs + NB * ai_group_doubles(b, BC > 0));
     // the row's state lives in the workgroup's global slot
     double* g = scratch + (int64_t)blockIdx.x * gstride;
     AiState S;
@@ -1262,10 +1269,14 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, const chf_pattern_s* P0, int tma
     const size_t static_lds = AD_MAXP * 4 + 8 * 4 + 64 + 2 * 64 * 4;
     // the row's state (Kinv, V, Vt and the candidates) lives in the
     // workgroup's global slot; LDS holds the b x b work buffers
-    const size_t dyn = (size_t)ai_lds_doubles(b, (int)maxrow) * 8;
+    // (block sizes 10 and 21 run their own instantiation, whose candidate
+    // factorisations are register-resident)
+    const bool reg = b == 10 || b == 21;
+    const size_t dyn = (size_t)ai_lds_doubles(b, (int)maxrow, reg) * 8;
     CHF_CHECK(dyn + static_lds <= (size_t)lim, CHF_EINVAL, "adaptive pattern: block size too large for LDS");
     const int cus = device_cu_count();
-    const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / (dyn + static_lds + 512)));
+    // LDS is allocated in 512-byte granules
+    const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / ((dyn + static_lds + 511) / 512 * 512)));
     const int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, nb);
     const int64_t stride = (ai_global_doubles(Mmax, b, cap) + 31) / 32 * 32;
     DevBuf<double> scratch((size_t)grid * stride);
