@@ -214,8 +214,8 @@ def c2_leg(args, chf, torch, dev):
     del p
     stream = torch.cuda.current_stream()
     out = {"workload": (f"triharmonic-like 2D PUM-shaped A=R^T(L^3 (x) I_b)R, {n}x{n} patches, b={b}, {N} dofs, "
-                        f"{L}-level Galerkin V({k},{k}), cubic patch transfer, adaptive t_max={cfg.tmax}, "
-                        f"PCG rtol {cfg.rtol:g}"), "nnzb_A": nnzb}
+                        f"{L}-level Galerkin V({k},{k}), cubic patch transfer, finest transfer "
+                        f"P = R^-1 (P_s (x) I_b), adaptive t_max={cfg.tmax}, PCG rtol {cfg.rtol:g}"), "nnzb_A": nnzb}
     x64 = None
     for name, dt in [("fp64", chf.F64), ("mixed_f32", chf.F32), ("mixed_bf16g", chf.BF16),
                      ("fp64_bf16g", chf.F64_BF16G)]:
@@ -653,7 +653,8 @@ def main():
         "config": {
             "workload": (f"biharmonic-like 2D PUM-shaped A=R^T(L^2 (x) I_b)R, {n}x{n} patches, b={b}, "
                          f"{N} dofs, adaptive block-FSAI t_max={args.tmax}, fourth-kind Chebyshev degree {k}, "
-                         f"{L}-level Galerkin V({k},{k}) PCG"),
+                         f"{L}-level Galerkin V({k},{k}) PCG, bilinear patch transfer with Dirichlet nodes, "
+                         f"finest transfer P = R^-1 (P_s (x) I_b)"),
             "patches": n, "block": b, "ndof": N, "nnzb_A": nnzb, "nnzb_G": nnzg, "degree": k,
             "tmax": args.tmax, "levels": L, "rhs": "N(0,1) seed 0",
         },
