@@ -978,9 +978,8 @@ __device__ __forceinline__ void ai_row(int k, int b, int tmax, double thresh, in
             if (e >= 0) mark[e - r0] = 1;
         }
         // Kinv <- bordered inverse (packed rows keep their offsets as M grows).
-        // Rows i < M: Kinv_ij += Vt_i . Vt_j; each lane walks its elements
-        // with (i, j) advanced incrementally and the next element's operands
-        // loaded while one is formed.
+        // Rows i < M: Kinv_ij += Vt_i . Vt_j; each lane walks its elements of
+        // the packed rows with (i, j) advanced incrementally.
         {
             const int64_t top = ai_tri(M);
             const int ln = ai_lane();
