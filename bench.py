@@ -104,22 +104,30 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(n, b, tmax, degree, target_s=10.0):
+def cpu_baseline(n, b, tmax, degree, target_s=10.0, levels=3):
     """The oracle (plain FP64 NumPy/SciPy) on a bounded sample of the same
     workload: a smaller patch grid of the same generator, block size, adaptive
-    pattern, degree and smoother. Only the smoother applications are timed."""
-    from oracle import adaptive, chebyshev, fsai, lanczos
+    pattern, degree and smoother. The headline value times the smoother
+    applications; beside it, each labelled, the oracle's Algorithm 1 and block
+    FSAI set-up on that grid, the rest of a `levels`-level hierarchy
+    (Galerkin products, Lanczos bounds, coarse factor) and PCG to 1e-8 with
+    V(degree, degree)."""
+    from oracle import adaptive, chebyshev, fsai, lanczos, multilevel
     from oracle.bsr import from_problem
-    from problems import lanczos_starts, make_problem, rhs
+    from problems import grid_sizes, lanczos_starts, level_basis, make_problem, prolongator, rhs
     p = make_problem(n, 2, b, 2, seed=0)
     a = from_problem(p)
+    sizes = grid_sizes(n, levels)
+    starts = lanczos_starts(0, [s_ * s_ * b for s_ in sizes])
     t0 = time.perf_counter()
     prow, pcol = adaptive.adaptive_pattern(a, tmax)
+    pattern_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
     g = fsai.fsai(a, prow, pcol)
+    fsai_s = time.perf_counter() - t0
     asp, gsp = a.scipy(), g.scipy()
     gtsp = gsp.T.tocsr()
-    beta, _ = lanczos.lmax(lambda v: gsp @ (asp @ (gtsp @ v)), lanczos_starts(0, [p.ndof])[0])
-    setup_s = time.perf_counter() - t0
+    beta, _ = lanczos.lmax(lambda v: gsp @ (asp @ (gtsp @ v)), starts[0])
     bvec = rhs(0, p.ndof)
     x = np.zeros(p.ndof)
     reps = 0
@@ -131,6 +139,33 @@ def cpu_baseline(n, b, tmax, degree, target_s=10.0):
         if el >= target_s or reps >= 100000:
             break
     t_app = el / reps
+    # the rest of the hierarchy, then PCG (level 0 reuses the pattern and factor above)
+    t0 = time.perf_counter()
+    pro = [prolongator(sizes[l + 1], 2) for l in range(levels - 1)]
+    bases = level_basis(p, levels)
+    hier, al = [], a
+    for l in range(levels):
+        lev = multilevel.Level(a=al)
+        if l == levels - 1:
+            lev.finish()
+            lev.chol = multilevel.coarse_factor(al)
+            hier.append(lev)
+            break
+        if l == 0:
+            lev.g = g
+        else:
+            pr, pc = adaptive.adaptive_pattern(al, tmax)
+            lev.g = fsai.fsai(al, pr, pc)
+        lev.p_s, lev.basis = pro[l], bases[l]
+        lev.finish()
+        lev.beta, _ = lanczos.lmax(lev.apply_b, np.asarray(starts[l]), 100, 1.01)
+        hier.append(lev)
+        al = multilevel.galerkin(al, pro[l], bases[l])
+    hier_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, pcg_it, _, pcg_tr = multilevel.pcg(hier[0].apply_a, lambda r: multilevel.vcycle(hier, 0, r, degree), bvec,
+                                          1e-8, 300)
+    pcg_s = time.perf_counter() - t0
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
@@ -140,8 +175,19 @@ def cpu_baseline(n, b, tmax, degree, target_s=10.0):
         "value": p.ndof * degree / t_app / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
         "sample": (f"{reps} oracle smoother applications (Algorithm 3, degree {degree}, SciPy BSR products, "
                    f"single-threaded) on a {n}x{n}-patch grid of the same generator (b={b}, {p.ndof} dofs, "
-                   f"adaptive t_max={tmax}); {el:.1f} s timed; oracle set-up {setup_s:.1f} s untimed; "
+                   f"adaptive t_max={tmax}); {el:.1f} s timed; "
                    f"host affinity {cores} cores, OMP_NUM_THREADS={threads}"),
+        "oracle_setup_and_solve": {
+            "grid": f"{n}x{n} patches, b={b}, {p.ndof} dofs, {levels} levels, V({degree},{degree})",
+            "adaptive_pattern_s": round(pattern_s, 2),
+            "fsai_setup_s": round(fsai_s, 2),
+            "fsai_setup_rows_per_s": round(p.nb / fsai_s, 1),
+            "rest_of_hierarchy_s": round(hier_s, 2),
+            "pcg_iterations": int(pcg_it),
+            "pcg_s": round(pcg_s, 2),
+            "pcg_true_relres": float(pcg_tr),
+            "note": "plain Python/NumPy/SciPy row loops, one core; not the GPU path's algorithms or layout",
+        },
     }
 
 
