@@ -680,12 +680,30 @@ __device__ inline void ai_init_slots(int k, int b, int s0, int s1, const int* __
             tmp_b[lane] = find_block(a_rowptr, a_col, k, c);
         }
         __syncthreads();
+        // four elements per pass, their loads issued together
 #pragma unroll 1
-        for (int t = lane; t < n * bb; t += 64) {
-            const int sl = t / bb, e = t - sl * bb;
-            const int ecc = tmp_a[sl], ekc = tmp_b[sl];
-            S.W[(int64_t)(c0 + sl) * bb + e] = ecc >= 0 ? a_vals[(int64_t)ecc * bb + e] : 0.0;
-            S.H[(int64_t)(c0 + sl) * bb + e] = ekc >= 0 ? a_vals[(int64_t)ekc * bb + e] : 0.0;
+        for (int t0 = lane; t0 < n * bb; t0 += 256) {
+            double wv[4], hv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + 64 * u;
+                wv[u] = hv[u] = 0.0;
+                if (t < n * bb) {
+                    const int sl = t / bb, e = t - sl * bb;
+                    const int ecc = tmp_a[sl], ekc = tmp_b[sl];
+                    if (ecc >= 0) wv[u] = a_vals[(int64_t)ecc * bb + e];
+                    if (ekc >= 0) hv[u] = a_vals[(int64_t)ekc * bb + e];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = t0 + 64 * u;
+                if (t < n * bb) {
+                    const int sl = t / bb, e = t - sl * bb;
+                    S.W[(int64_t)(c0 + sl) * bb + e] = wv[u];
+                    S.H[(int64_t)(c0 + sl) * bb + e] = hv[u];
+                }
+            }
         }
         __syncthreads();
     }
