@@ -18,8 +18,12 @@ A second form keeps A, the vectors and the arithmetic in FP64 and rounds only
 G to BF16 (bf16g_levels): it halves the bytes of the two factor products per
 smoothing step while the cycle sees the exact operator.
 
-Parity of the mixed forms is unpinned beyond the roundings themselves: their
-error against the FP64 oracle is reported, not derived.
+The FP32 smoother (Algorithm 3 on the rounded A and G, FP32 vectors) is
+pinned by a forward rounding-error bound around the exact smoother on
+independently rounded operators. Parity unpinned: the rest of the mixed
+cycle (FP32 residual, restriction and prolongation, the coarse solve fed
+with FP32 data) and the outer PCG; their error against the FP64 oracle is
+reported, not derived.
 """
 from __future__ import annotations
 

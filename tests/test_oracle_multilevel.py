@@ -169,3 +169,56 @@ def test_basis_transfer_pcg_iterations_bounded():
         _, it, _, _ = multilevel.pcg(lv[0].apply_a, lambda r: multilevel.vcycle(lv, 0, r, 3), rhs(0, p.ndof), 1e-8, 200)
         its.append(it)
     assert its[1] <= 15 and its[1] <= its[0] + 6
+
+
+def test_lanczos_reproduces_a_tridiagonal_operator():
+    # Started from e_1, the Lanczos recurrence on a symmetric tridiagonal
+    # matrix rebuilds that matrix (up to the signs of the basis vectors): for
+    # tridiag(-1, 2, -1) every alpha is 2 and every beta is 1, exactly, and
+    # the Ritz value after n steps is the largest eigenvalue 2 + 2 cos(pi/(n+1)).
+    n = 24
+    main = np.full(n, 2.0)
+    off = np.full(n - 1, -1.0)
+
+    def apply(v):
+        w = main * v
+        w[:-1] += off * v[1:]
+        w[1:] += off * v[:-1]
+        return w
+
+    v0 = np.zeros(n)
+    v0[0] = 1.0
+    alphas, betas = lanczos.lanczos_tridiag(apply, v0, n)
+    assert np.array_equal(alphas, np.full(n, 2.0))
+    assert np.array_equal(betas, np.full(n - 1, 1.0))
+    _, theta = lanczos.lmax(apply, v0, n, 1.0)
+    assert abs(theta - (2.0 + 2.0 * np.cos(np.pi / (n + 1)))) < 1e-13
+    # fewer steps: the Ritz value is the largest eigenvalue of the leading
+    # m x m block, 2 + 2 cos(pi/(m+1))
+    m = 7
+    _, theta_m = lanczos.lmax(apply, v0, m, 1.0)
+    assert abs(theta_m - (2.0 + 2.0 * np.cos(np.pi / (m + 1)))) < 1e-13
+
+
+def test_lanczos_ritz_values_of_the_krylov_space():
+    # After m steps the tridiagonal is the operator compressed to the Krylov
+    # space K_m(B, v0): its eigenvalues equal those of Q^T B Q for any
+    # orthonormal basis Q of that space (here from a QR of the Krylov matrix).
+    rng = np.random.default_rng(5)
+    n, m = 40, 6
+    qf, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    bm = qf @ np.diag(np.linspace(1.0, 3.0, n)) @ qf.T
+    v0 = rng.standard_normal(n)
+    alphas, betas = lanczos.lanczos_tridiag(lambda v: bm @ v, v0, m)
+    kry = np.empty((n, m))
+    kry[:, 0] = v0 / np.linalg.norm(v0)
+    for j in range(1, m):
+        kry[:, j] = bm @ kry[:, j - 1]
+    q, _ = np.linalg.qr(kry)
+    want = np.linalg.eigvalsh(q.T @ bm @ q)
+    t = np.diag(alphas) + np.diag(betas, 1) + np.diag(betas, -1)
+    got = np.linalg.eigvalsh(t)
+    assert np.abs(got - want).max() < 1e-10
+    # the first Ritz value is the Rayleigh quotient of the start vector
+    v = v0 / np.linalg.norm(v0)
+    assert abs(alphas[0] - v @ bm @ v) < 1e-14 * abs(alphas[0])
