@@ -18,12 +18,12 @@ A second form keeps A, the vectors and the arithmetic in FP64 and rounds only
 G to BF16 (bf16g_levels): it halves the bytes of the two factor products per
 smoothing step while the cycle sees the exact operator.
 
-The FP32 smoother (Algorithm 3 on the rounded A and G, FP32 vectors) is
-pinned by a forward rounding-error bound around the exact smoother on
-independently rounded operators. Parity unpinned: the rest of the mixed
-cycle (FP32 residual, restriction and prolongation, the coarse solve fed
-with FP32 data) and the outer PCG; their error against the FP64 oracle is
-reported, not derived.
+The FP32 smoother (Algorithm 3 on the rounded A and G, FP32 vectors) and the
+two-level mixed V-cycle (FP32 residual and transfers, FP64 coarse Cholesky
+fed with FP32 data) are pinned by forward rounding-error bounds around the
+exact smoother and cycle on independently rounded operators. The outer
+FP64 PCG wrapped around the mixed cycle is not pinned beyond that; its
+iteration counts are compared with the FP64 form.
 """
 from __future__ import annotations
 

@@ -1,8 +1,8 @@
 """Mixed precision (A and G stored in FP32, G optionally BF16, FP32 vectors
 and accumulation inside the V-cycle, FP64 outer PCG): per-application error
 against the FP64 oracle and convergence of the outer PCG. The oracle's FP32
-smoother is pinned by a rounding-error bound (test_oracle_mixed_bound.py);
-the rest of the mixed cycle is not. The bounds below follow from
+smoother and mixed cycle are pinned by rounding-error bounds
+(test_oracle_mixed_bound.py). The bounds below follow from
 the unit roundoffs (FP32 6e-8, BF16 3.9e-3) times the smoother's modest
 amplification."""
 import numpy as np

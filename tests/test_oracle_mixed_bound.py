@@ -24,6 +24,8 @@ the oracle's rounding functions, so the pin also checks which rounding each
 operator received: the BF16-G smoother is compared with the FP32-G exact
 smoother too, and must fall outside the bound there.
 """
+import functools
+
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -132,11 +134,13 @@ def _bound(a, g, gt, x0, beta, k, rec, u):
     return 1.01 * total
 
 
+@functools.lru_cache(maxsize=None)
 def _level(b, pw, shift, n=8):
     """One smoothed level (and its coarse level) of the PUM-shaped operator,
     with shift * max_i sum_j |a_ij| added to the diagonal when shift > 0 (a
     well-conditioned operator of the same structure, on which the bound is
-    tight enough to tell a BF16 G from an FP32 one)."""
+    tight enough to tell a BF16 G from an FP32 one). Cached: the tests only
+    read the hierarchy."""
     p = make_problem(n, 2, b, pw, seed=0)
     a = from_problem(p)
     if shift:
@@ -192,3 +196,150 @@ def test_mixed_smoother_within_rounding_bound(b, pw, store, k, zero, shift):
         rec6 = _run(a6, g6, gt6, bv, x0, lev.beta, k, np.float64)
         wrong = float(np.linalg.norm(rec32[0] - rec6[0]))
         assert wrong > e32 + _bound(a6, g6, gt6, x0, lev.beta, k, rec6, U64), (wrong, e32)
+
+
+def _smoother_propagator(ma, beta, k):
+    """Exact map from the error of the start vector to the error of the
+    result of Algorithm 3 (increment form, E_d starts at zero)."""
+    n = ma.shape[0]
+    carry, scale = chebyshev.cheb4_coefficients(beta, k)
+    eye = np.eye(n)
+    prod = np.eye(2 * n)
+    for i in range(k - 1, -1, -1):
+        c, s = (0.0 if i == 0 else carry[i]), scale[i]
+        prod = prod @ np.block([[eye - s * ma, c * eye], [-s * ma, c * eye]])
+    return prod[:n, :n]
+
+
+@pytest.mark.parametrize("b", [3, 10])
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+@pytest.mark.parametrize("shift", [0.0, 0.2])
+@pytest.mark.parametrize("source", ["random", "coarse"])
+@pytest.mark.parametrize("k", [1, 3])
+def test_mixed_vcycle_within_rounding_bound(monkeypatch, b, store, shift, source, k):
+    """V(k,k) of the mixed hierarchy (two levels; FP32 smoothing, residual,
+    restriction and prolongation; FP64 Cholesky of the coarse Galerkin
+    operator fed with FP32 data, its result rounded to FP32) against the
+    exact cycle with the same stored operators. Local errors of each stage
+    (the smoother bounds above; gamma_n |P^T||r^| and gamma_n |P||x^_c| for
+    the transfers; Higham Thm. 10.4, |dA| <= gamma_{3n+1} |R^T||R| in FP64,
+    for the Cholesky solve, plus one FP32 rounding of its result) are carried
+    to the output by the exact maps of the stages after them. The "coarse"
+    right-hand side is A P v_c, whose solution lies in the coarse space, so
+    that the coarse correction carries a large part of the result (about a
+    quarter at k = 1 on these grids: there a coarse correction off by 1%
+    falls outside the bound)."""
+    p, levels, starts = _level(b, 2, shift)
+    ml = mixed.mixed_levels(levels, store, starts)
+    lev, lev64 = ml[0], levels[0]
+    assert lev.t is None and len(ml) == 2
+    n = p.ndof
+    # record what the cycle passes through the smoother and the transfers
+    smooth_recs, restr, prol = [], [], []
+    orig = chebyshev.cheb4
+
+    def rec_cheb4(apply_a, apply_m, bb, x0, beta, kk, x_is_zero=False):
+        xs, rs, ts, zs = [], [], [], []
+
+        def aa(v):
+            xs.append(np.asarray(v, dtype=np.float64).copy())
+            return apply_a(v)
+
+        def mm(v):
+            rs.append(np.asarray(v, dtype=np.float64).copy())
+            t = lev.g @ v
+            ts.append(np.asarray(t, dtype=np.float64).copy())
+            z = lev.gt @ t
+            zs.append(np.asarray(z, dtype=np.float64).copy())
+            return z
+
+        x = orig(aa, mm, bb, x0, beta, kk, x_is_zero=x_is_zero)
+        x0r = None if x_is_zero else np.asarray(x0, dtype=np.float64).copy()
+        smooth_recs.append((x0r, (np.asarray(x, dtype=np.float64), xs, rs, ts, zs)))
+        return x
+
+    r_orig, p_orig = lev.restrict, lev.prolong
+
+    def rec_restrict(r):
+        out = r_orig(r)
+        restr.append((np.asarray(r, dtype=np.float64).copy(), np.asarray(out, dtype=np.float64).copy()))
+        return out
+
+    def rec_prolong(xc):
+        out = p_orig(xc)
+        prol.append((np.asarray(xc, dtype=np.float64).copy(), np.asarray(out, dtype=np.float64).copy()))
+        return out
+
+    monkeypatch.setattr(mixed.chebyshev, "cheb4", rec_cheb4)
+    monkeypatch.setattr(lev, "restrict", rec_restrict)
+    monkeypatch.setattr(lev, "prolong", rec_prolong)
+    if source == "random":
+        bv = rhs(0, n).astype(np.float32)
+    else:
+        pfull = sp.kron(lev64.p_s, sp.identity(b), format="csr")
+        bv = (lev64.a.scipy() @ (pfull @ rhs(1, pfull.shape[1]))).astype(np.float32)
+    x_mixed = np.asarray(mixed.vcycle_mixed(ml, 0, bv, k), dtype=np.float64)
+    monkeypatch.undo()
+    assert len(smooth_recs) == 2 and len(restr) == 1 and len(prol) == 1
+
+    # the stored operators, rounded independently, and the exact cycle on them
+    def ops(g_store):
+        a64 = sp.bsr_matrix((_round_torch(lev64.a.vals, "f32"), lev64.a.colidx, lev64.a.rowptr), shape=(n, n))
+        g64 = sp.bsr_matrix((_round_torch(lev64.g.vals, g_store), lev64.g.colidx, lev64.g.rowptr), shape=(n, n))
+        pb = sp.kron(lev64.p_s, sp.identity(b), format="csr")
+        pb = sp.csr_matrix((_round_torch(pb.data, "f32"), pb.indices, pb.indptr), shape=pb.shape)
+        return a64, g64, g64.T.tobsr(blocksize=(b, b)), pb
+
+    ac = levels[1].a.dense()
+    ac_inv = np.linalg.inv(ac)
+    b64 = bv.astype(np.float64)
+
+    def exact_cycle(a64, g64, gt64, pb):
+        ad, gd = a64.toarray(), g64.toarray()
+        ma = gd.T @ gd @ ad
+        pd = pb.toarray()
+        e_s = _smoother_propagator(ma, lev.beta, k)
+        # the smoother from zero is (I - E_s) A^{-1} b; written without A^{-1}
+        # through the recurrence itself, in FP64
+        apply_a = lambda v: a64 @ v  # noqa: E731
+        apply_m = lambda v: gt64 @ (g64 @ v)  # noqa: E731
+        x1 = orig(apply_a, apply_m, b64, None, lev.beta, k, x_is_zero=True)
+        x2 = x1 + pd @ np.linalg.solve(ac, pd.T @ (b64 - a64 @ x1))
+        x3 = orig(apply_a, apply_m, b64, x2, lev.beta, k)
+        return x3, ad, pd, e_s
+
+    a64, g64, gt64, pb = ops(store)
+    x_ref, ad, pd, e_post = exact_cycle(a64, g64, gt64, pb)
+
+    u = U32
+    nrm = lambda v: float(np.linalg.norm(v))  # noqa: E731
+    n2 = lambda m: float(np.linalg.norm(m, 2))  # noqa: E731
+    (x0_pre, rec_pre), (x0_post, rec_post) = smooth_recs
+    assert x0_pre is None
+    b_pre = _bound(a64, g64, gt64, None, lev.beta, k, rec_pre, u)
+    b_post = _bound(a64, g64, gt64, x0_post, lev.beta, k, rec_post, u)
+    x1 = rec_pre[0]
+    r_in, _ = restr[0]
+    xc, _ = prol[0]
+    # stage errors
+    na, npt, npr = _max_row_terms(a64), _max_row_terms(pb.T), _max_row_terms(pb)
+    f_r = nrm(_gamma(na, u) * (abs(ad) @ abs(x1)) + _gamma(1, u) * abs(r_in))
+    f_p = nrm(_gamma(npt, u) * (abs(pd).T @ abs(r_in)))
+    nc = ac.shape[0]
+    rfac = np.linalg.cholesky(ac).T
+    f_c = n2(ac_inv) * nrm(_gamma(3 * nc + 1, U64) * (abs(rfac.T) @ (abs(rfac) @ abs(xc)))) + nrm(_gamma(1, u) * abs(xc))
+    f_y = nrm(_gamma(npr, u) * (abs(pd) @ abs(xc)))
+    x2 = x0_post
+    f_add = nrm(_gamma(1, u) * abs(x2))
+    coarse = pd @ ac_inv @ pd.T
+    bound = (n2(e_post @ (np.eye(n) - coarse @ ad)) * b_pre + n2(e_post @ coarse) * f_r
+             + n2(e_post @ pd @ ac_inv) * f_p + n2(e_post @ pd) * (f_c + f_y) + n2(e_post) * f_add + b_post)
+    # the FP64 evaluation of the reference: far below the FP32 terms
+    bound = 1.01 * bound + 1e-12 * nrm(x_ref)
+    diff = nrm(x_mixed - x_ref)
+    size = nrm(x_ref)
+    assert diff <= bound, (diff, bound)
+    assert 0.0 < diff and bound < (1e-1 if shift == 0.0 else 5e-3) * size, (diff, bound, size)
+    if store == "bf16" and shift > 0.0:
+        x_wrong = exact_cycle(*ops("f32"))[0]
+        assert nrm(x_mixed - x_wrong) > bound, (nrm(x_mixed - x_wrong), bound)
