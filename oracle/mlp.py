@@ -71,6 +71,19 @@ def loss_grad(p, x, y):
     return lval, g
 
 
+def adam_step(p, g, m, v, t: int, lr: float, beta1: float, beta2: float, eps: float):
+    """One Adam update (Kingma and Ba, 2015, Algorithm 1), step t >= 1, in
+    FP64: first and second moment estimates, their bias corrections by
+    1 - beta^t, and the parameter move lr * m_hat / (sqrt(v_hat) + eps).
+    Returns the new (p, m, v). The network's optimiser; not in the paper."""
+    g = np.asarray(g, dtype=np.float64)
+    m = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    m_hat = m / (1.0 - beta1 ** t)
+    v_hat = v / (1.0 - beta2 ** t)
+    return np.asarray(p, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps), m, v
+
+
 def a2_candidates(a: Bsr):
     """Strictly lower part of the row pattern of A^2, rows ascending."""
     rowptr, cols = [0], []

@@ -174,3 +174,36 @@ def test_learned_pattern_gain_over_adaptive(chf):
           f"rows identical to Algorithm 1: {same}; rho_A {rho}")
     assert t_ml < t_ad
     assert rho["learned"] <= 1.05 * rho["adaptive"]
+
+
+def test_train_steps_match_oracle_adam(chf):
+    """Three chf_mlp_train_step calls on one batch against the oracle's FP64
+    backprop and Adam (Kingma and Ba, Algorithm 1) from the same start. The
+    GPU gradient is FP32 (within 1e-4 of the FP64 one); Adam divides each
+    gradient by its own magnitude, so a parameter whose FP64 gradient sits
+    below the FP32 resolution may move by up to lr the other way. All but a
+    few parameters must agree to lr * 1e-3 (plus the FP32 rounding of w),
+    and every one to 2 lr per step."""
+    import torch
+    rng = np.random.default_rng(4)
+    params = mlp_init(3)
+    n = 4096
+    x = rng.standard_normal((n, mlp.NIN)).astype(np.float32)
+    y = (x[:, 0] - 0.3 * x[:, 2] > 0.1).astype(np.float32)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    net = chf.mlp_create(params)
+    xd, yd = dev(x), dev(y)
+    p = params.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    x64, y64 = x.astype(np.float64), y.astype(np.float64)
+    for t in range(1, 4):
+        loss = chf.mlp_train_step(net, xd, yd, n, lr=lr, beta1=b1, beta2=b2, eps=eps)
+        wl, g = mlp.loss_grad(p, x64, y64)
+        assert abs(loss - wl) < 1e-5 * abs(wl), (t, loss, wl)
+        p, m, v = mlp.adam_step(p, g, m, v, t, lr, b1, b2, eps)
+        got = chf.mlp_get_params(net).astype(np.float64)
+        err = np.abs(got - p)
+        tol = lr * 1e-3 + 1e-6 * np.abs(p)
+        assert err.max() <= 2 * lr * t, (t, err.max())
+        assert np.count_nonzero(err > tol) <= 5, (t, np.count_nonzero(err > tol))

@@ -88,3 +88,30 @@ def test_labels_hand_built():
     prow = np.array([0, 1, 2, 4])
     pcol = np.array([0, 1, 0, 2])
     assert list(mlp.labels(crow, ccol, prow, pcol)) == [0.0, 1.0, 0.0]
+
+
+def test_adam_closed_forms():
+    """Adam from zero moments: with bias correction the first move is
+    lr g / (|g| + eps) whatever beta1, beta2; a constant gradient keeps
+    m_hat = g and v_hat = g^2, so every move is the same; a gradient that
+    flips sign at step 2 gives m_hat = -(1 - beta1) / (1 + beta1) g and
+    v_hat = g^2."""
+    rng = np.random.default_rng(3)
+    n = 50
+    p0 = rng.standard_normal(n)
+    g = rng.standard_normal(n) * 10.0 ** rng.uniform(-6, 1, n)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    z = np.zeros(n)
+    p1, m1, v1 = mlp.adam_step(p0, g, z, z, 1, lr, b1, b2, eps)
+    step = lr * g / (np.abs(g) + eps)
+    assert np.allclose(p1, p0 - step, rtol=0, atol=1e-15)
+    p, m, v = p0, z, z
+    for t in range(1, 6):
+        p, m, v = mlp.adam_step(p, g, m, v, t, lr, b1, b2, eps)
+    assert np.allclose(p, p0 - 5 * step, rtol=0, atol=1e-14)
+    p2, _, _ = mlp.adam_step(p1, -g, m1, v1, 2, lr, b1, b2, eps)
+    want = p1 + lr * ((1 - b1) / (1 + b1)) * g / (np.abs(g) + eps)
+    assert np.allclose(p2, want, rtol=0, atol=1e-14)
+    # a zero gradient leaves the parameter where it is
+    pz, _, _ = mlp.adam_step(p0, z, z, z, 1, lr, b1, b2, eps)
+    assert np.array_equal(pz, p0)
