@@ -13,6 +13,10 @@
  *  - Host arrays are read during the call only and never retained.
  *  - Device vectors are caller-owned buffers on the current HIP device;
  *    handles own their device memory and free it in the matching *_destroy.
+ *    At block size 10 the products read vectors in pairs, so a vector that
+ *    enters a product must start on a 16-byte (double) or 8-byte (float)
+ *    boundary, as hipMalloc'd and torch buffers do; other addresses are
+ *    rejected with CHF_EINVAL.
  *  - `stream` is the caller's HIP stream (0 = null stream). A call returns
  *    after enqueueing work, except where a scalar must come back to the host
  *    (PCG stop test, Lanczos, set-up calls), which synchronise `stream`.

@@ -545,6 +545,11 @@ void sell_spmv(const Sell& A, chf_dtype vec, const void* x, void* y, const void*
         vsell_spmv(A, vec, x, y, bvec, epi, p, xo, alpha, beta, s);
         return;
     }
+    // b = 10 kernels read x in pairs (8 bytes for FP32 vectors, 16 for FP64)
+    if (A.b == 10) {
+        const uintptr_t need = vec == CHF_F64 ? 16 : 8;
+        CHF_CHECK((uintptr_t)x % need == 0, CHF_EINVAL, "vector not aligned to 16 bytes (FP64) or 8 bytes (FP32)");
+    }
     if (A.dtype == CHF_F64) {
         CHF_CHECK(vec == CHF_F64, CHF_EINVAL, "FP64 operator needs FP64 vectors");
         launch_spmv_b<double, double>(A, x, y, bvec, epi, p, xo, alpha, beta, s);

@@ -178,6 +178,24 @@ def test_error_bad_inputs(chf):
         chf.cheb4_smooth(A, G, 1.0, 0, z, z, work=torch.zeros(3 * p.ndof, dtype=torch.float64, device="cuda"))
 
 
+def test_error_misaligned_vector(chf):
+    """At b = 10 the products read x in pairs: a vector that does not start on
+    a 16-byte (FP64) boundary is rejected on the host before any launch; the
+    same product on an aligned copy runs."""
+    import torch
+    p = make_problem(4, 2, 10, 2, seed=0)
+    A = upload(p)
+    buf = torch.zeros(p.ndof + 2, dtype=torch.float64, device="cuda")
+    x_bad = buf[1:1 + p.ndof]
+    assert x_bad.data_ptr() % 16 == 8
+    y = torch.zeros(p.ndof, dtype=torch.float64, device="cuda")
+    with pytest.raises(chf.ChfError) as ei:
+        chf.bsr_spmv(A, x_bad, y)
+    assert ei.value.code == -1
+    chf.bsr_spmv(A, buf[2:2 + p.ndof], y)
+    torch.cuda.synchronize()
+
+
 def test_empty_matrix(chf):
     A = chf.bsr_create(0, 3, np.zeros(1, np.int64), np.zeros(0, np.int32), np.zeros((0, 3, 3)))
     assert A.info() == (0, 3, 0)
