@@ -36,6 +36,8 @@
  *    workgroup per slice (default 2048; 0 = never).
  *  - CHF_SPMV_NONTEMPORAL=0: plain instead of non-temporal matrix loads
  *    (read once per process).
+ *  - CHF_AI_WG_PER_CU=<n>: at most n rows of chf_pattern_adaptive in flight
+ *    per compute unit (default: as many as LDS and registers allow).
  */
 #ifndef CHF_H
 #define CHF_H

@@ -1293,7 +1293,10 @@ chf_pattern_s* adaptive_pattern_impl(chf_bsr A, const chf_pattern_s* P0, int tma
     CHF_CHECK(dyn + static_lds <= (size_t)lim, CHF_EINVAL, "adaptive pattern: block size too large for LDS");
     const int cus = device_cu_count();
     // LDS is allocated in 512-byte granules
-    const int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / ((dyn + static_lds + 511) / 512 * 512)));
+    int per_cu = std::max<int>(1, (int)std::min<size_t>(8, (size_t)lim / ((dyn + static_lds + 511) / 512 * 512)));
+    // CHF_AI_WG_PER_CU=<n> lowers the number of resident rows per CU (fewer
+    // row states in flight, each more likely to stay in the caches)
+    if (const char* e = std::getenv("CHF_AI_WG_PER_CU")) per_cu = std::max(1, std::min(per_cu, std::atoi(e)));
     const int64_t grid = std::min<int64_t>((int64_t)cus * per_cu, nb);
     const int64_t stride = (ai_global_doubles(Mmax, b, cap) + 31) / 32 * 32;
     DevBuf<double> scratch((size_t)grid * stride);
