@@ -191,6 +191,54 @@ def cpu_baseline(n, b, tmax, degree, target_s=10.0, levels=3):
     }
 
 
+def cpu_setup3d_sample(g, b, tmax, target_s=10.0, max_rows=4096):
+    """The oracle's Algorithm 1 and block-FSAI set-up on a sample of rows of
+    the 3D set-up workload (g^3 patches, t_max from P0 = diagonal), beside
+    the GPU's whole-matrix times: rows spread evenly over the middle third of
+    the grid (interior rows, the 262,064-of-262,144 majority at 64^3), taken
+    in a fixed stratified order until about target_s seconds have passed; a
+    per-row rate, labelled as a sample."""
+    from oracle import adaptive, fsai
+    from oracle.bsr import from_problem
+    from problems import make_problem
+    t0 = time.perf_counter()
+    a = from_problem(make_problem(g, 3, b, 2, seed=0))
+    gen_s = time.perf_counter() - t0
+    lo, span = a.nb // 3, a.nb // 3
+    # strata: max_rows evenly spaced rows, visited in bit-reversed order so
+    # that any prefix of the visit covers the middle third evenly
+    nbits = max(1, (max_rows - 1).bit_length())
+    order = [int(format(i, f"0{nbits}b")[::-1], 2) for i in range(1 << nbits)]
+    order = [o for o in order if o < max_rows]
+    pat_s = fsai_s = 0.0
+    done, sizes = [], []
+    for o in order:
+        k = int(lo + o * span // max_rows)
+        t0 = time.perf_counter()
+        prow, pcol = adaptive.adaptive_pattern(a, tmax, rows=[k])
+        pat_s += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fsai.fsai_row(a, k, pcol[prow[0]:prow[1]])
+        fsai_s += time.perf_counter() - t0
+        done.append(k)
+        sizes.append(int(prow[1] - prow[0]))
+        if pat_s + fsai_s >= target_s:
+            break
+    return {
+        "sample": (f"sampled: {len(done)} interior rows of the {g}^3-patch workload (b={b}, {a.nb} block rows), "
+                   f"evenly spread over the middle third, Algorithm 1 with t_max={tmax} from P0 = diagonal, "
+                   "then each row's block-FSAI solve; plain Python/NumPy row loops, BLAS threads "
+                   f"OMP_NUM_THREADS={os.environ.get('OMP_NUM_THREADS', 'unset')}"),
+        "rows": len(done),
+        "pattern_blocks_per_row_mean": round(float(np.mean(sizes)), 2),
+        "adaptive_pattern_s_per_row": round(pat_s / len(done), 4),
+        "fsai_setup_s_per_row": round(fsai_s / len(done), 5),
+        "adaptive_pattern_rows_per_s": round(len(done) / pat_s, 2),
+        "fsai_setup_rows_per_s": round(len(done) / fsai_s, 1),
+        "generator_s": round(gen_s, 1),
+    }
+
+
 def setup3d_leg(args, chf, torch):
     """Batched block-FSAI set-up of the 3D biharmonic-like workload: Algorithm 1
     with t_max = 23 from P0 = diagonal gives local systems of 1..24 blocks
@@ -803,6 +851,9 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on the host")
         out["cpu_baseline"] = cpu_baseline(args.cpu_grid, b, args.tmax, k)
+        if not args.no_setup3d:
+            out["cpu_baseline"]["oracle_setup3d_sampled"] = cpu_setup3d_sample(args.setup3d_grid, b,
+                                                                               args.setup3d_tmax)
     print(json.dumps(out), flush=True)
 
 
