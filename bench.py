@@ -583,8 +583,8 @@ def learned_leg(args, chf, torch, dev, n, b, L, k, pro, bases_unused):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the multi-GPU form of this path is a design note, "
-              "not part of this build (run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: the path has no multi-GPU implementation "
+              "(its sharding is described, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2509_06744_amd as chf

@@ -320,7 +320,7 @@ int chf_bicgstab_solve(chf_levels L, const double* b, double* x, double rtol, in
 /* ------------------------------------------------------- learned pattern -- */
 /* Not part of the paper: a small network, trained on patterns that Algorithm 1
  * produces, proposes the factor pattern; Algorithm 1 stays the fallback and
- * the reference it is judged against. */
+ * the reference its patterns are compared against. */
 /* Candidate features for the learned pattern proposer: for each block row k
  * and each candidate c in the strictly lower part of the row pattern of A^2,
  * 6 FP32 features: ||A_kc||_F, ||A_cc^{-1} A_ck||_F, the signed patch offset (dx, dy, dz) of c from k
